@@ -1,0 +1,88 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake (a swapped weight, a wrong sign or index, a
+dropped term) in a copy of the oracle's C source, builds it on the CPU, and
+checks that at least one pin of ``test_oracle_pins`` fails against it, while
+the unmodified source passes them all.  CPU only.
+"""
+import os
+
+import pytest
+
+from oracle import oracle as O
+import test_oracle_pins as T
+
+# (name, original text, planted mistake)
+MUTANTS = [
+    ("deposit weights swapped", "rho[j0] += (1.0 - f) * qdx;", "rho[j0] += f * qdx;"),
+    ("node offset sign", "double t = x / cell_width(p) - 0.5;", "double t = x / cell_width(p) + 0.5;"),
+    ("fixed half-cell shift sign", "int64_t Us = U - ((int64_t)1 << 31);", "int64_t Us = U + ((int64_t)1 << 31);"),
+    ("fixed right node index", "S[wrap_index(j + 1, ng)] += F;", "S[wrap_index(j - 1, ng)] += F;"),
+    ("fixed left weight", "S[wrap_index(j, ng)] += ((int64_t)1 << 32) - F;", "S[wrap_index(j, ng)] += F;"),
+    ("solve drops mean", "run += (rho[g] - mean) * dx;", "run += rho[g] * dx;"),
+    ("solve sign", "run += (rho[g] - mean) * dx;", "run -= (rho[g] - mean) * dx;"),
+    ("solve neighbour index", "double left = face[g == 0 ? ng - 1 : g - 1];",
+     "double left = face[g + 1 < ng ? g + 1 : 0];"),
+    ("solve drops gauge constant", "face[g] -= c;", "face[g] -= 0.0 * c;"),
+    ("kick sign", "double v_new = v_old + p->qm * Ep[i] * p->dt;", "double v_new = v_old - p->qm * Ep[i] * p->dt;"),
+    ("drift with old velocity", "x[i] = wrap_position(p, x[i] + v_new * p->dt);",
+     "x[i] = wrap_position(p, x[i] + v_old * p->dt);"),
+    ("gather weights swapped", "Ep[i] = (1.0 - f) * E[j0] + f * E[j1];", "Ep[i] = f * E[j0] + (1.0 - f) * E[j1];"),
+    ("field energy factor", "return 0.5 * s * cell_width(p);", "return s * cell_width(p);"),
+    ("charge sign", "double s = p->qm < 0.0 ? -1.0 : 1.0;", "double s = p->qm < 0.0 ? 1.0 : -1.0;"),
+    ("wrap with ceil", "x -= p->L * floor(x / p->L);", "x -= p->L * ceil(x / p->L);"),
+    ("kinetic energy factor", "row[0] = 0.25 * m * (acc[0] + acc[1]);", "row[0] = 0.5 * m * (acc[0] + acc[1]);"),
+    ("cg beta inverted", "double beta = rr_new / rr;", "double beta = rr / rr_new;"),
+    ("cg pinned row", "r[g] = g == 0 ? 0.0 : -rho[g] * dx * dx;", "r[g] = -rho[g] * dx * dx;"),
+]
+
+# The pins run against every build (argument lists for the parametrised ones).
+PINS = [
+    (T.test_plain_deposit_matches_triangle_bruteforce, [(2,), (4,), (8,)]),
+    (T.test_fixed_deposit_total_is_exact_and_matches_bruteforce, [(3,), (8,)]),
+    (T.test_fixed_deposit_hand_derived_golden_cases, [()]),
+    (T.test_fixed_density_matches_plain_density, [()]),
+    (T.test_solve_matches_dense_linear_algebra, [(8,), (17,)]),
+    (T.test_solve_single_mode_closed_form, [(16, 1), (64, 3)]),
+    (T.test_paper_cg_converges_to_exact_solve, [(32,)]),
+    (T.test_gather_on_nodes_and_linear_field, [()]),
+    (T.test_push_uniform_field_closed_form, [()]),
+    (T.test_push_wraps_periodically, [()]),
+    (T.test_momentum_is_conserved_to_rounding, [()]),
+    (T.test_single_particle_feels_no_self_force, [(0.123,), (1.777,)]),
+    (T.test_energy_conservation_two_stream, [()]),
+    (T.test_cold_plasma_oscillates_at_the_discrete_plasma_frequency, [()]),
+]
+
+
+def failing_pins():
+    failed = []
+    for fn, arglists in PINS:
+        for args in arglists:
+            try:
+                fn(*args)
+            except Exception as e:  # a crash of a broken build also counts as caught
+                failed.append(f"{fn.__name__}{args}: {type(e).__name__}")
+    return failed
+
+
+@pytest.fixture
+def restore_oracle():
+    yield
+    O.use_library(None)
+
+
+def test_unmodified_oracle_passes_every_pin(restore_oracle):
+    O.use_library(None)
+    assert failing_pins() == []
+
+
+@pytest.mark.parametrize("name,orig,bad", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(name, orig, bad, tmp_path, restore_oracle):
+    src = open(O.SRC).read()
+    assert src.count(orig) == 1, f"mutation anchor not unique: {orig}"
+    mutant = tmp_path / "mutant.c"
+    mutant.write_text(src.replace(orig, bad))
+    so = O.build(str(mutant), str(tmp_path / f"libmutant_{abs(hash(name))}.so"))
+    O.use_library(so)
+    assert failing_pins(), f"no pin caught the planted mistake: {name}"
