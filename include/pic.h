@@ -1,0 +1,211 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) engine for the 1D electrostatic
+ * particle-in-cell (PIC) cycle of S. Markidis and G. Lapenta, "Development and
+ * performance analysis of a UPC Particle-in-Cell code" (PGAS10).
+ *
+ * Model (Sec. 2): one dimension, electrostatic, mobile electrons of charge-to-
+ * mass ratio qm over an immobile uniform ion background rho0, periodic domain
+ * [0, L) split into ng cells of width dx = L/ng with nodes at (g + 1/2) dx
+ * (Appendix A), epsilon_0 = 1.  One step advances the state
+ * (x^n, v^{n-1/2}, E^n) to (x^{n+1}, v^{n+1/2}, E^{n+1}):
+ *   1. linear (two-node) gather of E^n at each particle (Sec. 2.3);
+ *   2. leapfrog kick v^{n+1/2} = v^{n-1/2} + qm E_p^n dt (Sec. 2.1);
+ *   3. drift x^{n+1} = x^n + v^{n+1/2} dt and periodic wrap (Sec. 2.1);
+ *   4. linear charge deposit with the same two-node weights (Sec. 2.3),
+ *      particle charge Q = sign(qm) rho0 L / np (Appendix A);
+ *   5. periodic three-point Poisson solve and central-difference field
+ *      (Sec. 2.2), solved exactly with zero-mean potential.
+ *
+ * Numerics.  Particle state and push in FP32 (PIC_FP32) or FP64 (PIC_FP64).
+ * Internally a particle is stored as u = x/dx in [0, ng) and w = v dt/dx.
+ * The deposit is exact fixed point: with U = floor(u 2^32) (exact, from the
+ * bits of u), j = floor((U - 2^31) / 2^32) and F = U - 2^31 - j 2^32, node
+ * j mod ng receives 2^32 - F and node j+1 mod ng receives F as int64, so the
+ * grid sum S_g is independent of summation order and sum_g S_g = np 2^32
+ * exactly; rho_g = rho0 + (Q/dx) 2^-32 S_g.  Solve and diagnostics in FP64.
+ *
+ * Ownership.  Host arrays passed in are borrowed for the call and copied.
+ * A caller-provided device buffer (dev_mem) is borrowed for the lifetime of
+ * the run and must be at least pic_footprint() bytes, 256-byte aligned; with
+ * dev_mem == NULL the library allocates (and later frees) its own.  Output
+ * arrays are caller-allocated with explicit capacities.
+ *
+ * Errors.  Every call returns a pic_status; negative values are errors and
+ * pic_last_error() then holds a thread-local message.  Nothing is thrown
+ * across the ABI and nothing aborts.  Device faults of asynchronous work
+ * surface at the next synchronising call as PIC_EDEVICE, after which the run
+ * is sticky in PIC_ESTATE.  Calls on one handle must be serialised by the
+ * caller; different handles may be used from different threads.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  All
+ * device work of a run or batch is enqueued on its stream.
+ */
+#ifndef PIC1D_PIC_H
+#define PIC1D_PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,   /* invalid argument or parameter                      */
+    PIC_ENOMEM = -2,   /* device or host allocation failed / buffer too small */
+    PIC_EDEVICE = -3,  /* HIP runtime or device error                         */
+    PIC_ESTATE = -4,   /* handle in an error state, or call out of order      */
+    PIC_EBUDGET = -5   /* batch: the run does not fit the HBM budget now      */
+} pic_status;
+
+typedef enum { PIC_FP32 = 0, PIC_FP64 = 1 } pic_precision;
+
+/* Run parameters (Appendix A lists the paper's: L, ng, np, dt, qm, rho0).
+ * Validation: ng in [2, PIC_MAX_NG]; 1 <= np < 2^31; L > 0; dt > 0;
+ * qm != 0; rho0 > 0; all finite; precision PIC_FP32 or PIC_FP64. */
+typedef struct pic_params {
+    double  L;            /* periodic domain length                          */
+    int32_t ng;           /* cells = grid nodes                              */
+    int32_t precision;    /* pic_precision of the particle state and push    */
+    int64_t np;           /* computational particles                         */
+    double  dt;           /* time step                                       */
+    double  qm;           /* charge-to-mass ratio (electrons: -1)            */
+    double  rho0;         /* ion background density (paper: 1)              */
+    int32_t sort_every;   /* cell sort every K steps; 0 = engine default, <0 never */
+    int32_t tile;         /* particles per tile (multiple of 256); 0 = default */
+    int64_t history_cap;  /* per-step history rows kept on the device        */
+} pic_params;
+
+#define PIC_MAX_NG 8192
+
+/* Diagnostics of the current state (x^N, v^{N-1/2}, E^N) after N steps. */
+typedef struct pic_diag {
+    int64_t  step;             /* N                                            */
+    double   time;             /* N dt                                         */
+    double   kinetic;          /* (m/2) sum_p (v_p^{N-1/2})^2, m = Q/qm        */
+    double   field;            /* W_E^N = (1/2) sum_g (E_g^N)^2 dx              */
+    double   momentum;         /* m sum_p v_p^{N-1/2}                          */
+    int64_t  charge_fixed_sum; /* sum_g S_g of the deposit of x^N (= np 2^32)  */
+    double   net_charge;       /* sum_g rho_g dx (ions + particles)            */
+    uint32_t flags;            /* PIC_FLAG_* seen since creation              */
+    uint32_t pad_;
+} pic_diag;
+
+#define PIC_FLAG_NONFINITE 1u  /* a non-finite position was reset to 0       */
+#define PIC_FLAG_MULTIWRAP 2u  /* a particle moved more than L in one step   */
+
+/* One row per step n (0-based) of the per-step history:
+ *   [0] KE^n  = (m/4) sum_p ((v^{n-1/2})^2 + (v^{n+1/2})^2)  (time-centred)
+ *   [1] W_E^n = field energy of E^n, the field that step n gathers
+ *   [2] P^{n+1/2} = m sum_p v^{n+1/2}
+ *   [3] K^{n+1/2} = (m/2) sum_p (v^{n+1/2})^2                            */
+#define PIC_HIST_COLS 4
+
+typedef struct pic_run pic_run;
+typedef struct pic_batch pic_batch;
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *pic_last_error(void);
+
+/* Library version string. */
+const char *pic_version(void);
+
+/* Device bytes a run with these parameters needs (state, sort scratch, grids,
+ * per-tile partials, history, descriptor).  EINVAL on invalid parameters. */
+pic_status pic_footprint(const pic_params *params, size_t *bytes);
+
+/* Create a run from host positions x0[np] in [0, L) and velocities
+ * v_mhalf[np] (the velocity at t = -dt/2, the leapfrog half step of Sec. 2.1),
+ * both FP64 and copied.  Requires max |v| dt < L (one wrap per step).
+ * Deposits x0 and solves for E^0 on the device (enqueued on `stream`).
+ * dev_mem/dev_bytes: see Ownership above.  On success *out owns the run. */
+pic_status pic_create(const pic_params *params, const double *x0, const double *v_mhalf,
+                      void *dev_mem, size_t dev_bytes, void *stream, pic_run **out);
+
+/* Enqueue `nsteps` >= 0 steps (asynchronous; returns before they run).
+ * Every `sort_every` steps the particles are first reordered by cell. */
+pic_status pic_step(pic_run *run, int64_t nsteps);
+
+/* Same as pic_step but the steps are replayed from a captured HIP graph of
+ * `graph_steps` launches (captured on first use, reused afterwards). */
+pic_status pic_step_graph(pic_run *run, int64_t nsteps, int32_t graph_steps);
+
+/* Synchronise the run's stream and report diagnostics of the current state.
+ * rho_out/E_out (FP64, ng_cap >= ng entries) may be NULL. */
+pic_status pic_diagnostics(pic_run *run, pic_diag *diag, double *rho_out, double *E_out,
+                           int32_t ng_cap);
+
+/* Synchronise and copy the particles out in physical units
+ * (x = u dx, v^{N-1/2} = w dx/dt) in their current storage order (the cell
+ * sort permutes them).  cap >= np. */
+pic_status pic_read_particles(pic_run *run, double *x, double *v, int64_t cap);
+
+/* Synchronise and copy the raw engine state: u[np], w[np] in the run's
+ * precision (float for PIC_FP32, double for PIC_FP64). cap >= np. */
+pic_status pic_read_raw(pic_run *run, void *u, void *w, int64_t cap);
+
+/* Synchronise and copy the fixed-point sums S[ng] of the current positions,
+ * the FP64 node field E[ng] and the FP32 gather table Ehat[ng] =
+ * float(E qm dt^2/dx).  Any pointer may be NULL; cap >= ng. */
+pic_status pic_read_grid(pic_run *run, int64_t *S, double *E, float *Ehat, int32_t cap);
+
+/* Synchronise and copy history rows [first, first+count) (PIC_HIST_COLS
+ * doubles each).  Rows beyond min(steps taken, history_cap) are EINVAL. */
+pic_status pic_read_history(pic_run *run, int64_t first, int64_t count, double *rows);
+
+/* Wait for the run's queued work, release what the library allocated. */
+pic_status pic_destroy(pic_run *run);
+
+/* ---------------------------------------------------------------------
+ * Batched engine and continuous-batching service.
+ *
+ * A batch steps many independent runs of different (np, ng) with one
+ * persistent fused kernel launch per step, replayed from a captured HIP
+ * graph.  Runs are admitted at any time against an HBM budget (bytes of the
+ * batch's device arena), keep their state resident, stop at their own step
+ * count and release their memory on pic_batch_release.  The result of a run
+ * is the same alone and in any mix: its tiles, deposit and solve depend only
+ * on its own (np, ng).
+ * ------------------------------------------------------------------- */
+typedef struct pic_batch_config {
+    size_t  hbm_budget;    /* bytes of the device arena for run state        */
+    void   *arena;         /* caller device buffer of hbm_budget bytes, or NULL */
+    int32_t max_runs;      /* run-table capacity                              */
+    int32_t ng_max;        /* largest ng admitted (sizes the LDS)             */
+    int32_t graph_steps;   /* kernel launches captured per graph              */
+    int32_t grid_blocks;   /* persistent workgroups; 0 = device default       */
+} pic_batch_config;
+
+pic_status pic_batch_create(const pic_batch_config *cfg, void *stream, pic_batch **out);
+
+/* Admit a run that will take `nsteps` steps.  PIC_EBUDGET if its footprint
+ * does not fit the arena now (nothing is changed; retry after releases).
+ * The initial deposit and solve are enqueued immediately. */
+pic_status pic_batch_admit(pic_batch *b, const pic_params *params, const double *x0,
+                           const double *v_mhalf, int64_t nsteps, int64_t *run_id);
+
+/* Advance every unfinished run by up to `nsteps` steps (asynchronous). */
+pic_status pic_batch_step(pic_batch *b, int64_t nsteps);
+
+/* Report runs that reached their step count since the last poll
+ * (non-blocking: only completed device work is reported). */
+pic_status pic_batch_poll(pic_batch *b, int64_t *done_ids, int32_t cap, int32_t *n_done);
+
+/* Borrow the pic_run view of a batch member, valid until its release; the
+ * read/diagnostic calls above work on it (pic_step/pic_destroy do not). */
+pic_status pic_batch_run(pic_batch *b, int64_t run_id, pic_run **view);
+
+/* Free a run's arena space (waits for the batch's queued work first). */
+pic_status pic_batch_release(pic_batch *b, int64_t run_id);
+
+/* Bytes of the arena in use / free, and runs admitted and not released. */
+pic_status pic_batch_usage(pic_batch *b, size_t *used, size_t *free_bytes, int32_t *nruns);
+
+pic_status pic_batch_destroy(pic_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC1D_PIC_H */

@@ -1,0 +1,79 @@
+// Internal declarations shared by the device kernels (pic_kernels.hip) and
+// the host runtime (pic_runtime.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic1d {
+
+constexpr int kMaxNg = 8192;
+constexpr int kHistCols = 4;
+constexpr int kPartCols = 4;     // per tile: sum w_old^2, sum w_new^2, sum w_new, unused
+constexpr int kWave = 64;
+
+// Device-resident descriptor of one run.  Lives in device memory; the
+// kernels update step/counter/flags and the "now" diagnostics.
+struct RunDev {
+    void *u, *w;                 // state: u = x/dx in [0, ng), w = v dt/dx
+    void *u_alt, *w_alt;         // cell-sort destination (ping-pong), may be null
+    unsigned long long *S;       // [ng] fixed-point charge sums, zero between steps
+    unsigned long long *S_last;  // [ng] copy of S from the latest solve
+    float *Ehat;                 // [ng] gather table  E qm dt^2 / dx   (FP32)
+    double *Ehat64;              // [ng] same table in FP64 (FP64 state), may be null
+    double *E64;                 // [ng] node field (FP64)
+    double *tile_part;           // [ntiles][kPartCols]
+    double *hist;                // [hist_cap][kHistCols]
+    uint32_t *sort_hist;         // [nsort_blocks][ng] per-block cell counts
+    int64_t np;
+    int64_t hist_cap;
+    int64_t step;                // steps completed
+    int64_t step_target;         // no further steps once step == step_target
+    int32_t ng;
+    int32_t tile;                // particles per tile (multiple of 256)
+    int32_t ntiles;
+    int32_t precision;           // 0 = FP32 state, 1 = FP64 state
+    uint32_t counter;            // tiles finished in the current pass
+    uint32_t flags;              // PIC_FLAG_* bits
+    double dx;
+    double qfac;                 // Q / (dx 2^32): density per unit of S
+    double ecoef;                // qm dt^2 / dx: E -> change of w per step
+    double kcoef;                // (m/2) (dx/dt)^2: sum w^2 -> kinetic energy
+    double pcoef;                // m dx/dt: sum w -> momentum
+    double field_now;            // W_E of the current field
+    double kinetic_now;          // (m/2) sum v^2 of the current velocities
+    double momentum_now;
+    int64_t charge_now;          // sum_g S_g of the current positions
+    int32_t sort_swap;           // 1 when the sorted copy lives in u_alt/w_alt
+    int32_t pad_;
+};
+
+// One unit of schedule: tiles [tile_begin, tile_end) of run `run`.
+struct WorkItem {
+    int32_t run;
+    int32_t tile_begin;
+    int32_t tile_end;
+    int32_t pad_;
+};
+
+// Kernel launchers (pic_kernels.hip).  All enqueue on `stream` and return
+// the launch status.
+//   items == nullptr: single run `runs[0]`, tiles split evenly over `grid`
+//   workgroups.  Otherwise workgroup b processes items[wg_begin[b] ..
+//   wg_begin[b+1]).
+//   prologue != 0: deposit + solve only (creation), no push.
+hipError_t launch_step(RunDev *runs, const WorkItem *items, const int32_t *wg_begin,
+                       int grid, int block, int ng_lds, int precision, int prologue,
+                       hipStream_t stream);
+
+// Allow the step kernels of this block size/precision the LDS they need
+// (called once before the first launch and before any graph capture).
+hipError_t step_prepare(int block, int precision);
+
+// Largest resident workgroups per CU for the step kernel.
+int step_occupancy(int block, int ng_lds, int precision);
+
+// Dynamic LDS of one workgroup: the int64 grid plus the gather table.
+size_t step_lds_bytes(int precision, int ng_lds);
+
+}  // namespace pic1d

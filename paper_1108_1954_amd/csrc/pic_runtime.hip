@@ -1,0 +1,953 @@
+// Host runtime of the PIC engine: parameter validation, device layout,
+// run lifecycle, graph replay, and the batched engine (device arena
+// allocator, run table, LPT work schedule, continuous admission).
+// Implements the C ABI declared in include/pic.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pic.h"
+#include "pic_internal.h"
+
+using namespace pic1d;
+
+// ------------------------------------------------------------------ errors --
+
+static thread_local std::string g_err;
+
+static pic_status fail(pic_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(PIC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+extern "C" const char *pic_last_error(void) { return g_err.c_str(); }
+extern "C" const char *pic_version(void) { return "pic1d-gfx950 1.0"; }
+
+// ------------------------------------------------------------ device info --
+
+namespace {
+
+struct DeviceInfo {
+    int cus = 256;
+    int block = 512;
+};
+
+DeviceInfo device_info() {
+    DeviceInfo d;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            d.cus = n;
+    }
+    if (const char *b = getenv("PIC1D_BLOCK")) {
+        int v = atoi(b);
+        if (v == 256 || v == 512 || v == 1024) d.block = v;
+    }
+    return d;
+}
+
+bool finite_pos(double v) { return std::isfinite(v); }
+
+pic_status validate(const pic_params *p) {
+    if (!p) return fail(PIC_EINVAL, "params is NULL");
+    if (!(finite_pos(p->L) && p->L > 0)) return fail(PIC_EINVAL, "L must be finite and > 0 (got %g)", p->L);
+    if (p->ng < 2 || p->ng > PIC_MAX_NG)
+        return fail(PIC_EINVAL, "ng must be in [2, %d] (got %d)", PIC_MAX_NG, p->ng);
+    if (p->np < 1 || p->np >= (int64_t)1 << 31)
+        return fail(PIC_EINVAL, "np must be in [1, 2^31) (got %lld)", (long long)p->np);
+    if (!(finite_pos(p->dt) && p->dt > 0)) return fail(PIC_EINVAL, "dt must be finite and > 0");
+    if (!(std::isfinite(p->qm) && p->qm != 0)) return fail(PIC_EINVAL, "qm must be finite and nonzero");
+    if (!(finite_pos(p->rho0) && p->rho0 > 0)) return fail(PIC_EINVAL, "rho0 must be finite and > 0");
+    if (p->precision != PIC_FP32 && p->precision != PIC_FP64)
+        return fail(PIC_EINVAL, "precision must be PIC_FP32 or PIC_FP64");
+    if (p->tile < 0 || p->tile % 256 != 0 || p->tile > (1 << 20))
+        return fail(PIC_EINVAL, "tile must be 0 or a multiple of 256 up to 2^20 (got %d)", p->tile);
+    if (p->history_cap < 0) return fail(PIC_EINVAL, "history_cap must be >= 0");
+    return PIC_OK;
+}
+
+// Particles per tile: a pure function of (np, ng) so that every launch shape
+// sees the same tiles (and the same diagnostic summation order).
+int default_tile(int64_t np) {
+    int64_t t = 256;
+    while (t < 8192 && t * 8192 < np) t *= 2;
+    return (int)t;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    size_t u, w, S, S_last, Ehat, Ehat64, E64, part, hist, total;
+    int tile, ntiles;
+    size_t esize;
+};
+
+Layout make_layout(const pic_params *p) {
+    Layout L{};
+    L.esize = p->precision == PIC_FP64 ? 8 : 4;
+    L.tile = p->tile > 0 ? p->tile : default_tile(p->np);
+    L.ntiles = (int)((p->np + L.tile - 1) / L.tile);
+    const size_t np_pad = align_up((size_t)p->np, 64);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    L.u = take(np_pad * L.esize);
+    L.w = take(np_pad * L.esize);
+    L.S = take((size_t)p->ng * 8);
+    L.S_last = take((size_t)p->ng * 8);
+    L.Ehat = take((size_t)p->ng * 4);
+    L.Ehat64 = take((size_t)p->ng * 8);
+    L.E64 = take((size_t)p->ng * 8);
+    L.part = take((size_t)L.ntiles * kPartCols * 8);
+    L.hist = take((size_t)std::max<int64_t>(p->history_cap, 1) * kHistCols * 8);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- the run --
+
+struct pic_run {
+    pic_params p{};
+    Layout lay{};
+    char *base = nullptr;       // device memory of the run
+    bool owns_mem = false;
+    hipStream_t stream = nullptr;
+    RunDev host{};              // host mirror of the descriptor (pointers, constants)
+    RunDev *dev = nullptr;      // device descriptor (owned by the run or a batch slot)
+    bool owns_dev = false;
+    bool error = false;
+    bool batch_member = false;
+    int block = 512;
+    int grid = 1;
+    double Q = 0, m = 0, dx = 0;
+    // graph replay cache
+    hipGraphExec_t graph = nullptr;
+    int graph_steps = 0;
+};
+
+extern "C" pic_status pic_footprint(const pic_params *params, size_t *bytes) {
+    pic_status st = validate(params);
+    if (st != PIC_OK) return st;
+    if (!bytes) return fail(PIC_EINVAL, "bytes is NULL");
+    *bytes = make_layout(params).total + 256;   // + room for the descriptor
+    return PIC_OK;
+}
+
+namespace {
+
+pic_status check_particles(const pic_params *p, const double *x0, const double *v) {
+    if (!x0 || !v) return fail(PIC_EINVAL, "x0 and v_mhalf must not be NULL");
+    const double vmax_ok = p->L / p->dt;
+    for (int64_t i = 0; i < p->np; ++i) {
+        if (!(x0[i] >= 0.0 && x0[i] < p->L))
+            return fail(PIC_EINVAL, "x0[%lld] = %.17g outside [0, L)", (long long)i, x0[i]);
+        if (!(std::fabs(v[i]) < vmax_ok))
+            return fail(PIC_EINVAL, "v_mhalf[%lld] = %g: need finite |v| dt < L", (long long)i, v[i]);
+    }
+    return PIC_OK;
+}
+
+// Fill the descriptor constants (normalisation of Sec. 2 / Appendix A):
+// Q = sign(qm) rho0 L / np, m = Q/qm, ecoef = qm dt^2/dx, ...
+void fill_constants(pic_run *r) {
+    const pic_params &p = r->p;
+    r->dx = p.L / p.ng;
+    r->Q = (p.qm < 0 ? -1.0 : 1.0) * p.rho0 * p.L / (double)p.np;
+    r->m = r->Q / p.qm;
+    RunDev &h = r->host;
+    h.np = p.np;
+    h.ng = p.ng;
+    h.hist_cap = p.history_cap;
+    h.step = 0;
+    h.step_target = INT64_MAX;
+    h.tile = r->lay.tile;
+    h.ntiles = r->lay.ntiles;
+    h.precision = p.precision;
+    h.counter = 0;
+    h.flags = 0;
+    h.dx = r->dx;
+    h.qfac = r->Q / (r->dx * 4294967296.0);
+    h.ecoef = p.qm * p.dt * p.dt / r->dx;
+    const double vs = r->dx / p.dt;     // w -> v
+    h.kcoef = 0.5 * r->m * vs * vs;
+    h.pcoef = r->m * vs;
+}
+
+void carve(pic_run *r) {
+    char *b = r->base;
+    const Layout &L = r->lay;
+    RunDev &h = r->host;
+    h.u = b + L.u;
+    h.w = b + L.w;
+    h.u_alt = h.w_alt = nullptr;
+    h.S = (unsigned long long *)(b + L.S);
+    h.S_last = (unsigned long long *)(b + L.S_last);
+    h.Ehat = (float *)(b + L.Ehat);
+    h.Ehat64 = r->p.precision == PIC_FP64 ? (double *)(b + L.Ehat64) : nullptr;
+    h.E64 = (double *)(b + L.E64);
+    h.tile_part = (double *)(b + L.part);
+    h.hist = (double *)(b + L.hist);
+    h.sort_hist = nullptr;
+}
+
+// Convert host FP64 particles to engine units and upload them.
+pic_status upload_particles(pic_run *r, const double *x0, const double *v) {
+    const pic_params &p = r->p;
+    const double inv_dx = 1.0 / r->dx;
+    const double wscale = p.dt / r->dx;
+    const size_t n = (size_t)p.np;
+    if (p.precision == PIC_FP32) {
+        std::vector<float> u(n), w(n);
+        const float ngf = (float)p.ng;
+        for (size_t i = 0; i < n; ++i) {
+            float ui = (float)(x0[i] / r->dx);
+            if (!(ui < ngf)) ui = 0.0f;   // x just below L can round to ng: same point as 0
+            u[i] = ui;
+            w[i] = (float)(v[i] * wscale);
+        }
+        (void)inv_dx;
+        HIP_TRY(hipMemcpyAsync(r->host.u, u.data(), n * 4, hipMemcpyHostToDevice, r->stream));
+        HIP_TRY(hipMemcpyAsync(r->host.w, w.data(), n * 4, hipMemcpyHostToDevice, r->stream));
+        HIP_TRY(hipStreamSynchronize(r->stream));
+    } else {
+        std::vector<double> u(n), w(n);
+        const double ngd = (double)p.ng;
+        for (size_t i = 0; i < n; ++i) {
+            double ui = x0[i] / r->dx;
+            if (!(ui < ngd)) ui = 0.0;
+            u[i] = ui;
+            w[i] = v[i] * wscale;
+        }
+        HIP_TRY(hipMemcpyAsync(r->host.u, u.data(), n * 8, hipMemcpyHostToDevice, r->stream));
+        HIP_TRY(hipMemcpyAsync(r->host.w, w.data(), n * 8, hipMemcpyHostToDevice, r->stream));
+        HIP_TRY(hipStreamSynchronize(r->stream));
+    }
+    return PIC_OK;
+}
+
+// Zero the grids, publish the descriptor and run the prologue (deposit of
+// x^0 and solve for E^0) for a single run.
+pic_status init_device_state(pic_run *r) {
+    HIP_TRY(hipMemsetAsync(r->host.S, 0, (size_t)r->p.ng * 8, r->stream));
+    HIP_TRY(hipMemsetAsync(r->host.S_last, 0, (size_t)r->p.ng * 8, r->stream));
+    HIP_TRY(hipMemsetAsync(r->host.tile_part, 0, (size_t)r->lay.ntiles * kPartCols * 8, r->stream));
+    HIP_TRY(hipMemcpyAsync(r->dev, &r->host, sizeof(RunDev), hipMemcpyHostToDevice, r->stream));
+    HIP_TRY(step_prepare(r->block, r->p.precision));
+    HIP_TRY(launch_step(r->dev, nullptr, nullptr, r->grid, r->block, r->p.ng, r->p.precision, 1,
+                        r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return PIC_OK;
+}
+
+int single_run_grid(const pic_run *r, const DeviceInfo &d) {
+    const int occ = step_occupancy(d.block, r->p.ng, r->p.precision);
+    const int waves = d.block / 64;
+    const int want = (r->lay.ntiles + waves - 1) / waves;
+    return std::max(1, std::min(want, d.cus * occ));
+}
+
+pic_status check_run(pic_run *r) {
+    if (!r) return fail(PIC_EINVAL, "run is NULL");
+    if (r->error) return fail(PIC_ESTATE, "run is in an error state after an earlier device error");
+    return PIC_OK;
+}
+
+pic_status sync_run(pic_run *r) {
+    hipError_t e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) {
+        r->error = true;
+        return fail(PIC_EDEVICE, "device error: %s", hipGetErrorString(e));
+    }
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" pic_status pic_create(const pic_params *params, const double *x0, const double *v_mhalf,
+                                 void *dev_mem, size_t dev_bytes, void *stream, pic_run **out) {
+    pic_status st = validate(params);
+    if (st != PIC_OK) return st;
+    if (!out) return fail(PIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    st = check_particles(params, x0, v_mhalf);
+    if (st != PIC_OK) return st;
+    pic_run *r = new pic_run();
+    r->p = *params;
+    r->lay = make_layout(params);
+    r->stream = (hipStream_t)stream;
+    const size_t need = r->lay.total + 256;
+    if (dev_mem) {
+        if ((uintptr_t)dev_mem % 256 != 0) {
+            delete r;
+            return fail(PIC_EINVAL, "dev_mem must be 256-byte aligned");
+        }
+        if (dev_bytes < need) {
+            delete r;
+            return fail(PIC_ENOMEM, "dev_bytes %zu < footprint %zu", dev_bytes, need);
+        }
+        r->base = (char *)dev_mem;
+    } else {
+        void *p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            delete r;
+            return fail(PIC_ENOMEM, "hipMalloc of %zu bytes failed", need);
+        }
+        r->base = (char *)p;
+        r->owns_mem = true;
+    }
+    r->dev = (RunDev *)(r->base + r->lay.total);
+    DeviceInfo d = device_info();
+    r->block = d.block;
+    fill_constants(r);
+    carve(r);
+    r->grid = single_run_grid(r, d);
+    st = upload_particles(r, x0, v_mhalf);
+    if (st == PIC_OK) st = init_device_state(r);
+    if (st != PIC_OK) {
+        std::string msg = g_err;
+        if (r->owns_mem) (void)hipFree(r->base);
+        delete r;
+        g_err = msg;
+        return st;
+    }
+    *out = r;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_step(pic_run *r, int64_t nsteps) {
+    pic_status st = check_run(r);
+    if (st != PIC_OK) return st;
+    if (r->batch_member) return fail(PIC_ESTATE, "batch members are stepped with pic_batch_step");
+    if (nsteps < 0) return fail(PIC_EINVAL, "nsteps must be >= 0");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipError_t e = launch_step(r->dev, nullptr, nullptr, r->grid, r->block, r->p.ng,
+                                   r->p.precision, 0, r->stream);
+        if (e != hipSuccess) {
+            r->error = true;
+            return fail(PIC_EDEVICE, "step launch failed: %s", hipGetErrorString(e));
+        }
+    }
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_step_graph(pic_run *r, int64_t nsteps, int32_t graph_steps) {
+    pic_status st = check_run(r);
+    if (st != PIC_OK) return st;
+    if (r->batch_member) return fail(PIC_ESTATE, "batch members are stepped with pic_batch_step");
+    if (nsteps < 0 || graph_steps < 1 || graph_steps > 4096)
+        return fail(PIC_EINVAL, "need nsteps >= 0 and graph_steps in [1, 4096]");
+    if (r->graph && r->graph_steps != graph_steps) {
+        (void)hipGraphExecDestroy(r->graph);
+        r->graph = nullptr;
+    }
+    if (!r->graph && nsteps >= graph_steps) {
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t le = hipSuccess;
+        for (int k = 0; k < graph_steps && le == hipSuccess; ++k)
+            le = launch_step(r->dev, nullptr, nullptr, r->grid, r->block, r->p.ng, r->p.precision, 0,
+                             r->stream);
+        hipError_t ce = hipStreamEndCapture(r->stream, &g);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(PIC_EDEVICE, "graph capture failed: %s",
+                        hipGetErrorString(le != hipSuccess ? le : ce));
+        }
+        hipError_t ie = hipGraphInstantiate(&r->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return fail(PIC_EDEVICE, "graph instantiate: %s", hipGetErrorString(ie));
+        r->graph_steps = graph_steps;
+    }
+    int64_t left = nsteps;
+    while (r->graph && left >= graph_steps) {
+        HIP_TRY(hipGraphLaunch(r->graph, r->stream));
+        left -= graph_steps;
+    }
+    return pic_step(r, left);
+}
+
+extern "C" pic_status pic_diagnostics(pic_run *r, pic_diag *diag, double *rho_out, double *E_out,
+                                      int32_t ng_cap) {
+    pic_status st = check_run(r);
+    if (st != PIC_OK) return st;
+    if (!diag) return fail(PIC_EINVAL, "diag is NULL");
+    if ((rho_out || E_out) && ng_cap < r->p.ng) return fail(PIC_EINVAL, "ng_cap < ng");
+    st = sync_run(r);
+    if (st != PIC_OK) return st;
+    RunDev d;
+    HIP_TRY(hipMemcpy(&d, r->dev, sizeof d, hipMemcpyDeviceToHost));
+    diag->step = d.step;
+    diag->time = (double)d.step * r->p.dt;
+    diag->kinetic = d.kinetic_now;
+    diag->field = d.field_now;
+    diag->momentum = d.momentum_now;
+    diag->charge_fixed_sum = d.charge_now;
+    diag->net_charge = r->p.rho0 * r->p.L + r->Q * ((double)d.charge_now / 4294967296.0);
+    diag->flags = d.flags;
+    diag->pad_ = 0;
+    if (rho_out) {
+        std::vector<unsigned long long> S((size_t)r->p.ng);
+        HIP_TRY(hipMemcpy(S.data(), r->host.S_last, S.size() * 8, hipMemcpyDeviceToHost));
+        const double qdx = r->Q / r->dx;
+        for (int g = 0; g < r->p.ng; ++g)
+            rho_out[g] = r->p.rho0 + qdx * ((double)S[g] / 4294967296.0);
+    }
+    if (E_out) HIP_TRY(hipMemcpy(E_out, r->host.E64, (size_t)r->p.ng * 8, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_read_raw(pic_run *r, void *u, void *w, int64_t cap) {
+    pic_status st = check_run(r);
+    if (st != PIC_OK) return st;
+    if (cap < r->p.np) return fail(PIC_EINVAL, "cap %lld < np %lld", (long long)cap, (long long)r->p.np);
+    st = sync_run(r);
+    if (st != PIC_OK) return st;
+    const size_t bytes = (size_t)r->p.np * r->lay.esize;
+    if (u) HIP_TRY(hipMemcpy(u, r->host.u, bytes, hipMemcpyDeviceToHost));
+    if (w) HIP_TRY(hipMemcpy(w, r->host.w, bytes, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_read_particles(pic_run *r, double *x, double *v, int64_t cap) {
+    pic_status st = check_run(r);
+    if (st != PIC_OK) return st;
+    if (cap < r->p.np) return fail(PIC_EINVAL, "cap %lld < np %lld", (long long)cap, (long long)r->p.np);
+    const size_t n = (size_t)r->p.np;
+    const double vs = r->dx / r->p.dt;
+    if (r->p.precision == PIC_FP32) {
+        std::vector<float> u(n), w(n);
+        st = pic_read_raw(r, u.data(), w.data(), cap);
+        if (st != PIC_OK) return st;
+        for (size_t i = 0; i < n; ++i) {
+            if (x) x[i] = (double)u[i] * r->dx;
+            if (v) v[i] = (double)w[i] * vs;
+        }
+    } else {
+        std::vector<double> u(n), w(n);
+        st = pic_read_raw(r, u.data(), w.data(), cap);
+        if (st != PIC_OK) return st;
+        for (size_t i = 0; i < n; ++i) {
+            if (x) x[i] = u[i] * r->dx;
+            if (v) v[i] = w[i] * vs;
+        }
+    }
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_read_grid(pic_run *r, int64_t *S, double *E, float *Ehat, int32_t cap) {
+    pic_status st = check_run(r);
+    if (st != PIC_OK) return st;
+    if (cap < r->p.ng) return fail(PIC_EINVAL, "cap %d < ng %d", cap, r->p.ng);
+    st = sync_run(r);
+    if (st != PIC_OK) return st;
+    const size_t ng = (size_t)r->p.ng;
+    if (S) HIP_TRY(hipMemcpy(S, r->host.S_last, ng * 8, hipMemcpyDeviceToHost));
+    if (E) HIP_TRY(hipMemcpy(E, r->host.E64, ng * 8, hipMemcpyDeviceToHost));
+    if (Ehat) HIP_TRY(hipMemcpy(Ehat, r->host.Ehat, ng * 4, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_read_history(pic_run *r, int64_t first, int64_t count, double *rows) {
+    pic_status st = check_run(r);
+    if (st != PIC_OK) return st;
+    st = sync_run(r);
+    if (st != PIC_OK) return st;
+    RunDev d;
+    HIP_TRY(hipMemcpy(&d, r->dev, sizeof d, hipMemcpyDeviceToHost));
+    const int64_t avail = std::min<int64_t>(d.step, r->p.history_cap);
+    if (first < 0 || count < 0 || first + count > avail)
+        return fail(PIC_EINVAL, "history rows [%lld, %lld) outside the %lld available",
+                    (long long)first, (long long)(first + count), (long long)avail);
+    if (count == 0) return PIC_OK;
+    if (!rows) return fail(PIC_EINVAL, "rows is NULL");
+    HIP_TRY(hipMemcpy(rows, r->host.hist + (size_t)first * kHistCols,
+                      (size_t)count * kHistCols * 8, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_destroy(pic_run *r) {
+    if (!r) return PIC_OK;
+    if (r->batch_member) return fail(PIC_ESTATE, "batch members are released with pic_batch_release");
+    hipError_t e = hipStreamSynchronize(r->stream);
+    if (r->graph) (void)hipGraphExecDestroy(r->graph);
+    if (r->owns_mem) (void)hipFree(r->base);
+    delete r;
+    if (e != hipSuccess) return fail(PIC_EDEVICE, "device error at destroy: %s", hipGetErrorString(e));
+    return PIC_OK;
+}
+
+// ============================================================ batched engine
+
+namespace {
+
+// First-fit allocator over a device arena, 256-byte granules, coalescing.
+class Arena {
+  public:
+    void reset(size_t bytes) {
+        free_.clear();
+        size_ = bytes / 256 * 256;
+        if (size_) free_[0] = size_;
+        used_ = 0;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = align_up(std::max<size_t>(bytes, 1), 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                size_t rest = it->second - bytes;
+                size_t at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align_up(std::max<size_t>(bytes, 1), 256);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+    size_t size() const { return size_; }
+
+  private:
+    std::map<size_t, size_t> free_;
+    size_t size_ = 0, used_ = 0;
+};
+
+struct Member {
+    int64_t id;
+    int slot;
+    pic_run *run;          // view (descriptor lives in the batch's run table)
+    size_t off, bytes;     // arena span
+    int64_t nsteps;        // steps requested
+    int64_t launch_done;   // batch launch index after which the run is complete
+    bool reported = false;
+};
+
+}  // namespace
+
+struct pic_batch {
+    pic_batch_config cfg{};
+    hipStream_t stream = nullptr;
+    char *arena_base = nullptr;
+    bool owns_arena = false;
+    Arena arena;
+    RunDev *table = nullptr;          // device run table [max_runs]
+    WorkItem *items_dev = nullptr;    // device work list
+    int32_t *wg_dev = nullptr;        // device per-workgroup offsets [grid + 1]
+    WorkItem *items_host = nullptr;   // pinned staging
+    int32_t *wg_host = nullptr;
+    hipEvent_t staged = nullptr;      // staging buffers free again
+    int item_cap = 0;
+    int grid = 0, block = 512;
+    std::vector<int> free_slots;
+    std::map<int64_t, Member> members;
+    int64_t next_id = 1;
+    int64_t launches = 0;             // batch step launches issued
+    bool dirty = true;                // work list needs a rebuild
+    hipGraphExec_t graph = nullptr;
+    std::vector<std::pair<int64_t, hipEvent_t>> marks;   // (launch count, event)
+    int64_t launches_complete = 0;
+    bool error = false;
+};
+
+namespace {
+
+pic_status batch_check(pic_batch *b) {
+    if (!b) return fail(PIC_EINVAL, "batch is NULL");
+    if (b->error) return fail(PIC_ESTATE, "batch is in an error state after a device error");
+    return PIC_OK;
+}
+
+// Longest-processing-time assignment of chunks to the persistent workgroups.
+// Each run is split into chunks of about `target` particles (whole tiles);
+// chunks go, largest first, to the least-loaded workgroup.
+pic_status rebuild_schedule(pic_batch *b) {
+    struct Chunk {
+        int slot, tb, te;
+        int64_t work;
+    };
+    std::vector<Chunk> chunks;
+    int64_t total = 0;
+    for (auto &kv : b->members) {
+        const Member &m = kv.second;
+        if (m.launch_done <= b->launches) continue;   // finished: no work
+        total += m.run->p.np;
+    }
+    const int64_t target = std::max<int64_t>(1, total / std::max(1, 2 * b->grid));
+    for (auto &kv : b->members) {
+        const Member &m = kv.second;
+        if (m.launch_done <= b->launches) continue;
+        const int tile = m.run->lay.tile, nt = m.run->lay.ntiles;
+        const int per = (int)std::max<int64_t>(1, (target + tile - 1) / tile);
+        for (int t0 = 0; t0 < nt; t0 += per) {
+            int t1 = std::min(nt, t0 + per);
+            int64_t w = std::min<int64_t>((int64_t)t1 * tile, m.run->p.np) - (int64_t)t0 * tile;
+            chunks.push_back({m.slot, t0, t1, w + 4 * m.run->p.ng});
+        }
+    }
+    std::sort(chunks.begin(), chunks.end(), [](const Chunk &a, const Chunk &c) {
+        if (a.work != c.work) return a.work > c.work;
+        if (a.slot != c.slot) return a.slot < c.slot;
+        return a.tb < c.tb;
+    });
+    std::vector<std::vector<WorkItem>> per_wg((size_t)b->grid);
+    std::vector<int64_t> load((size_t)b->grid, 0);
+    for (const Chunk &c : chunks) {
+        size_t k = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[k] += c.work;
+        per_wg[k].push_back({c.slot, c.tb, c.te, 0});
+    }
+    if ((int)chunks.size() > b->item_cap)
+        return fail(PIC_ENOMEM, "work list of %zu chunks exceeds capacity %d", chunks.size(), b->item_cap);
+    HIP_TRY(hipEventSynchronize(b->staged));
+    int n = 0;
+    for (int k = 0; k < b->grid; ++k) {
+        b->wg_host[k] = n;
+        // consecutive chunks of one run stay together so the gather table is reused
+        std::sort(per_wg[(size_t)k].begin(), per_wg[(size_t)k].end(),
+                  [](const WorkItem &a, const WorkItem &c) {
+                      return a.run != c.run ? a.run < c.run : a.tile_begin < c.tile_begin;
+                  });
+        for (const WorkItem &w : per_wg[(size_t)k]) b->items_host[n++] = w;
+    }
+    b->wg_host[b->grid] = n;
+    HIP_TRY(hipMemcpyAsync(b->wg_dev, b->wg_host, sizeof(int32_t) * (size_t)(b->grid + 1),
+                           hipMemcpyHostToDevice, b->stream));
+    if (n) HIP_TRY(hipMemcpyAsync(b->items_dev, b->items_host, sizeof(WorkItem) * (size_t)n,
+                                  hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipEventRecord(b->staged, b->stream));
+    b->dirty = false;
+    return PIC_OK;
+}
+
+int64_t next_completion(const pic_batch *b) {
+    int64_t best = INT64_MAX;
+    for (auto &kv : b->members)
+        if (kv.second.launch_done > b->launches) best = std::min(best, kv.second.launch_done);
+    return best;
+}
+
+pic_status batch_launch_one(pic_batch *b) {
+    hipError_t e = launch_step(b->table, b->items_dev, b->wg_dev, b->grid, b->block, b->cfg.ng_max,
+                               PIC_FP32, 0, b->stream);
+    if (e != hipSuccess) {
+        b->error = true;
+        return fail(PIC_EDEVICE, "batch step launch failed: %s", hipGetErrorString(e));
+    }
+    return PIC_OK;
+}
+
+pic_status ensure_graph(pic_batch *b) {
+    if (b->graph || b->cfg.graph_steps <= 1) return PIC_OK;
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < b->cfg.graph_steps && le == hipSuccess; ++k)
+        le = launch_step(b->table, b->items_dev, b->wg_dev, b->grid, b->block, b->cfg.ng_max, PIC_FP32,
+                         0, b->stream);
+    hipError_t ce = hipStreamEndCapture(b->stream, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(PIC_EDEVICE, "batch graph capture failed: %s",
+                    hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    hipError_t ie = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(PIC_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(ie));
+    return PIC_OK;
+}
+
+pic_status add_mark(pic_batch *b) {
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ev, b->stream));
+    b->marks.push_back({b->launches, ev});
+    return PIC_OK;
+}
+
+void harvest_marks(pic_batch *b) {
+    size_t k = 0;
+    for (; k < b->marks.size(); ++k) {
+        hipError_t q = hipEventQuery(b->marks[k].second);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) {
+            b->error = true;
+            break;
+        }
+        b->launches_complete = std::max(b->launches_complete, b->marks[k].first);
+        (void)hipEventDestroy(b->marks[k].second);
+    }
+    b->marks.erase(b->marks.begin(), b->marks.begin() + (long)k);
+}
+
+}  // namespace
+
+extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream, pic_batch **out) {
+    if (!cfg || !out) return fail(PIC_EINVAL, "cfg and out must not be NULL");
+    *out = nullptr;
+    if (cfg->max_runs < 1 || cfg->max_runs > 65536) return fail(PIC_EINVAL, "max_runs must be in [1, 65536]");
+    if (cfg->ng_max < 2 || cfg->ng_max > PIC_MAX_NG) return fail(PIC_EINVAL, "ng_max must be in [2, %d]", PIC_MAX_NG);
+    if (cfg->graph_steps < 0 || cfg->graph_steps > 4096) return fail(PIC_EINVAL, "graph_steps must be in [0, 4096]");
+    if (cfg->hbm_budget < 4096) return fail(PIC_EINVAL, "hbm_budget too small");
+    if (cfg->arena && (uintptr_t)cfg->arena % 256) return fail(PIC_EINVAL, "arena must be 256-byte aligned");
+    pic_batch *b = new pic_batch();
+    b->cfg = *cfg;
+    b->stream = (hipStream_t)stream;
+    DeviceInfo d = device_info();
+    b->block = d.block;
+    hipError_t e = step_prepare(b->block, PIC_FP32);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(PIC_EDEVICE, "kernel setup: %s", hipGetErrorString(e));
+    }
+    const int occ = step_occupancy(b->block, cfg->ng_max, PIC_FP32);
+    b->grid = cfg->grid_blocks > 0 ? cfg->grid_blocks : d.cus * occ;
+    b->item_cap = 4 * b->grid + 4 * cfg->max_runs;
+    bool ok = true;
+    if (cfg->arena) {
+        b->arena_base = (char *)cfg->arena;
+    } else {
+        ok = hipMalloc((void **)&b->arena_base, cfg->hbm_budget) == hipSuccess;
+        b->owns_arena = ok;
+    }
+    ok = ok && hipMalloc((void **)&b->table, sizeof(RunDev) * (size_t)cfg->max_runs) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->items_dev, sizeof(WorkItem) * (size_t)b->item_cap) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->wg_dev, sizeof(int32_t) * (size_t)(b->grid + 1)) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&b->items_host, sizeof(WorkItem) * (size_t)b->item_cap) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&b->wg_host, sizeof(int32_t) * (size_t)(b->grid + 1)) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        pic_batch_destroy(b);
+        return fail(PIC_ENOMEM, "batch allocation failed");
+    }
+    b->arena.reset(cfg->hbm_budget);
+    for (int s = cfg->max_runs - 1; s >= 0; --s) b->free_slots.push_back(s);
+    if (hipEventRecord(b->staged, b->stream) != hipSuccess) {
+        pic_batch_destroy(b);
+        return fail(PIC_EDEVICE, "event record failed");
+    }
+    pic_status st = rebuild_schedule(b);
+    if (st != PIC_OK) {
+        std::string msg = g_err;
+        pic_batch_destroy(b);
+        g_err = msg;
+        return st;
+    }
+    *out = b;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, const double *x0,
+                                      const double *v_mhalf, int64_t nsteps, int64_t *run_id) {
+    pic_status st = batch_check(b);
+    if (st != PIC_OK) return st;
+    st = validate(params);
+    if (st != PIC_OK) return st;
+    if (!run_id) return fail(PIC_EINVAL, "run_id is NULL");
+    if (nsteps < 0) return fail(PIC_EINVAL, "nsteps must be >= 0");
+    if (params->precision != PIC_FP32) return fail(PIC_EINVAL, "batched runs use PIC_FP32 state");
+    if (params->ng > b->cfg.ng_max) return fail(PIC_EINVAL, "ng %d exceeds the batch's ng_max %d", params->ng, b->cfg.ng_max);
+    if (b->free_slots.empty()) return fail(PIC_EBUDGET, "run table full (%d runs)", b->cfg.max_runs);
+    st = check_particles(params, x0, v_mhalf);
+    if (st != PIC_OK) return st;
+    Layout lay = make_layout(params);
+    size_t off = 0;
+    if (!b->arena.alloc(lay.total, &off))
+        return fail(PIC_EBUDGET, "run needs %zu bytes; arena has %zu of %zu in use", lay.total,
+                    b->arena.used(), b->arena.size());
+    pic_run *r = new pic_run();
+    r->p = *params;
+    r->lay = lay;
+    r->stream = b->stream;
+    r->base = b->arena_base + off;
+    r->batch_member = true;
+    r->block = b->block;
+    const int slot = b->free_slots.back();
+    b->free_slots.pop_back();
+    r->dev = b->table + slot;
+    fill_constants(r);
+    carve(r);
+    r->host.step_target = nsteps;
+    r->grid = single_run_grid(r, device_info());
+    st = upload_particles(r, x0, v_mhalf);
+    if (st == PIC_OK) st = init_device_state(r);
+    if (st != PIC_OK) {
+        std::string msg = g_err;
+        b->arena.release(off, lay.total);
+        b->free_slots.push_back(slot);
+        delete r;
+        g_err = msg;
+        return st;
+    }
+    Member m;
+    m.id = b->next_id++;
+    m.slot = slot;
+    m.run = r;
+    m.off = off;
+    m.bytes = lay.total;
+    m.nsteps = nsteps;
+    m.launch_done = b->launches + nsteps;
+    b->members[m.id] = m;
+    b->dirty = true;
+    *run_id = m.id;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_batch_step(pic_batch *b, int64_t nsteps) {
+    pic_status st = batch_check(b);
+    if (st != PIC_OK) return st;
+    if (nsteps < 0) return fail(PIC_EINVAL, "nsteps must be >= 0");
+    int64_t left = nsteps;
+    while (left > 0) {
+        const int64_t nc = next_completion(b);
+        if (nc == INT64_MAX) break;                      // nothing left to run
+        if (b->dirty) {
+            st = rebuild_schedule(b);
+            if (st != PIC_OK) return st;
+        }
+        int64_t k = std::min(left, nc - b->launches);    // launches before membership changes
+        const int G = b->cfg.graph_steps;
+        if (G > 1 && k >= G) {
+            st = ensure_graph(b);
+            if (st != PIC_OK) return st;
+            while (k >= G) {
+                HIP_TRY(hipGraphLaunch(b->graph, b->stream));
+                b->launches += G;
+                left -= G;
+                k -= G;
+            }
+        }
+        for (; k > 0; --k, --left) {
+            st = batch_launch_one(b);
+            if (st != PIC_OK) return st;
+            b->launches += 1;
+        }
+        if (b->launches >= nc) b->dirty = true;          // some run just finished
+        st = add_mark(b);
+        if (st != PIC_OK) return st;
+    }
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_batch_poll(pic_batch *b, int64_t *done_ids, int32_t cap, int32_t *n_done) {
+    pic_status st = batch_check(b);
+    if (st != PIC_OK) return st;
+    if (!n_done || (cap > 0 && !done_ids)) return fail(PIC_EINVAL, "bad output arguments");
+    harvest_marks(b);
+    if (b->error) return fail(PIC_EDEVICE, "device error in batch work");
+    int32_t n = 0;
+    for (auto &kv : b->members) {
+        Member &m = kv.second;
+        if (m.reported || m.launch_done > b->launches_complete) continue;
+        if (n >= cap) break;
+        done_ids[n++] = m.id;
+        m.reported = true;
+    }
+    *n_done = n;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_batch_run(pic_batch *b, int64_t run_id, pic_run **view) {
+    pic_status st = batch_check(b);
+    if (st != PIC_OK) return st;
+    if (!view) return fail(PIC_EINVAL, "view is NULL");
+    auto it = b->members.find(run_id);
+    if (it == b->members.end()) return fail(PIC_EINVAL, "unknown run id %lld", (long long)run_id);
+    *view = it->second.run;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_batch_release(pic_batch *b, int64_t run_id) {
+    if (!b) return fail(PIC_EINVAL, "batch is NULL");
+    auto it = b->members.find(run_id);
+    if (it == b->members.end()) return fail(PIC_EINVAL, "unknown run id %lld", (long long)run_id);
+    // The arena span may still be read by queued launches.
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        b->error = true;
+        return fail(PIC_EDEVICE, "device error: %s", hipGetErrorString(e));
+    }
+    Member m = it->second;
+    b->members.erase(it);
+    // Park the slot: a descriptor whose step equals its target does no work.
+    RunDev idle{};
+    idle.step = 0;
+    idle.step_target = 0;
+    idle.ng = 2;
+    HIP_TRY(hipMemcpy(b->table + m.slot, &idle, sizeof idle, hipMemcpyHostToDevice));
+    b->arena.release(m.off, m.bytes);
+    b->free_slots.push_back(m.slot);
+    delete m.run;
+    b->dirty = true;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_batch_usage(pic_batch *b, size_t *used, size_t *free_bytes, int32_t *nruns) {
+    if (!b) return fail(PIC_EINVAL, "batch is NULL");
+    if (used) *used = b->arena.used();
+    if (free_bytes) *free_bytes = b->arena.size() - b->arena.used();
+    if (nruns) *nruns = (int32_t)b->members.size();
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_batch_destroy(pic_batch *b) {
+    if (!b) return PIC_OK;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    for (auto &kv : b->members) delete kv.second.run;
+    for (auto &mk : b->marks) (void)hipEventDestroy(mk.second);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    if (b->items_host) (void)hipHostFree(b->items_host);
+    if (b->wg_host) (void)hipHostFree(b->wg_host);
+    if (b->items_dev) (void)hipFree(b->items_dev);
+    if (b->wg_dev) (void)hipFree(b->wg_dev);
+    if (b->table) (void)hipFree(b->table);
+    if (b->owns_arena && b->arena_base) (void)hipFree(b->arena_base);
+    delete b;
+    if (e != hipSuccess) return fail(PIC_EDEVICE, "device error at destroy: %s", hipGetErrorString(e));
+    return PIC_OK;
+}

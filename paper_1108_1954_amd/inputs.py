@@ -111,18 +111,21 @@ def _beam_signs(n: int) -> np.ndarray:
 
 def random_phase_displacement(x0: np.ndarray, L: float, amp: float, nmodes: int,
                               seed: int, stream: int) -> np.ndarray:
-    """Displacement amp * sum_{m=1..M} sin(2 pi m x0 / L + phi_m), phi_m ~ U[0, 2 pi)."""
+    """Displacement amp * sum_{m=1..M} sin(2 pi m x0 / L + phi_m), phi_m ~ U[0, 2 pi).
+
+    The M-mode sum is evaluated exactly on a periodic table of K = 64 M
+    points and linearly interpolated at x0 (relative interpolation error
+    below (2 pi / 64)^2 / 8 = 1.2e-3 of the displacement), which keeps the
+    cost O(Np) for 10^8-particle inputs."""
     phi = 2.0 * math.pi * uniform(seed, stream, nmodes)
-    dx = np.zeros_like(x0)
+    K = 64 * max(1, nmodes)
+    xt = np.arange(K + 1) * (L / K)
     k0 = 2.0 * math.pi / L
-    for a in range(0, x0.size, _CHUNK):
-        b = min(x0.size, a + _CHUNK)
-        xs = x0[a:b]
-        acc = np.zeros_like(xs)
-        for m in range(1, nmodes + 1):
-            acc += np.sin(k0 * m * xs + phi[m - 1])
-        dx[a:b] = amp * acc
-    return dx
+    table = np.zeros(K + 1)
+    for m in range(1, nmodes + 1):
+        table += np.sin(k0 * m * xt + phi[m - 1])
+    table[K] = table[0]
+    return amp * np.interp(x0, xt, table)
 
 
 # --------------------------------------------------------------------------
@@ -148,10 +151,11 @@ def two_stream_small(seed: int = 1, np_: int = 10_000, nsteps: int = 200) -> Run
 
 
 def warm_two_stream_large(seed: int = 2, np_: int = 1 << 26, ng: int = 4096,
-                          nsteps: int = 1000) -> RunSpec:
+                          nsteps: int = 1000, L: Optional[float] = None) -> RunSpec:
     """Warm two-stream run: L=2.053*64, Ng=4096, Np=2^26, v=+-0.2 + 0.01 N(0,1),
-    random-phase displacement 1e-4 over M=min(128, Ng/2) modes, dt=0.1."""
-    L = 2.053 * 64
+    random-phase displacement 1e-4 over M=min(128, Ng/2) modes, dt=0.1.
+    Other sizes (and L) may be given for smaller cases of the same kind."""
+    L = 2.053 * 64 if L is None else float(L)
 
     def make():
         x0 = L * uniform(seed, 0, np_)

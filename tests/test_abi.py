@@ -1,0 +1,114 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/pic.h, and rejects invalid arguments before any device
+work (no compute calls here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1108_1954_amd import pic as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pic.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:pic_status|const\s+char\s*\*)\s*(pic_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(P.LIB_PATH):
+        from paper_1108_1954_amd import build
+        build.build()
+    return P.load()
+
+
+def test_header_declares_the_binding_symbols():
+    assert declared_functions() == sorted(P.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert P.pic_version().startswith("pic1d")
+
+
+def test_struct_layouts_match_header():
+    assert C.sizeof(P.pic_params) == 64
+    assert C.sizeof(P.pic_diag) == 64
+    assert C.sizeof(P.pic_batch_config) == 32
+
+
+def good(**kw):
+    d = dict(L=2.053, ng=64, np=1000, dt=0.1, history_cap=10)
+    d.update(kw)
+    return P.make_params(**d)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ng=1), dict(ng=P.PIC_MAX_NG + 1), dict(np=0), dict(np=1 << 31), dict(L=0.0),
+    dict(L=float("nan")), dict(dt=0.0), dict(dt=-1.0), dict(qm=0.0), dict(rho0=0.0),
+    dict(precision=2), dict(tile=100), dict(tile=-256), dict(history_cap=-1),
+])
+def test_footprint_rejects_invalid_parameters(lib, bad):
+    with pytest.raises(P.PicError) as e:
+        P.pic_footprint(good(**bad))
+    assert e.value.status == P.PIC_EINVAL
+    assert len(str(e.value)) > 10
+
+
+def test_footprint_counts_state_grids_and_history(lib):
+    n32 = P.pic_footprint(good(np=100_000))
+    n64 = P.pic_footprint(good(np=100_000, precision=P.PIC_FP64))
+    assert n32 >= 8 * 100_000 and n64 >= 16 * 100_000
+    assert n64 - n32 >= 8 * 100_000 - 4096
+    assert P.pic_footprint(good(history_cap=10_000)) - P.pic_footprint(good()) >= 32 * (10_000 - 10) - 512
+
+
+def test_create_validates_particles_before_device_work(lib):
+    p = good(np=4)
+    ok_x = np.array([0.0, 0.5, 1.0, 2.0])
+    ok_v = np.zeros(4)
+    for x, v in [
+        (np.array([0.0, 0.5, 1.0, 2.053]), ok_v),              # x == L
+        (np.array([-1e-9, 0.5, 1.0, 2.0]), ok_v),              # x < 0
+        (np.array([0.0, np.nan, 1.0, 2.0]), ok_v),             # NaN
+        (ok_x, np.array([0.0, 0.0, 30.0, 0.0])),               # |v| dt >= L
+        (ok_x, np.array([0.0, np.inf, 0.0, 0.0])),
+    ]:
+        with pytest.raises(P.PicError) as e:
+            P.pic_create(p, x, v)
+        assert e.value.status == P.PIC_EINVAL
+    with pytest.raises(ValueError):
+        P.pic_create(p, ok_x[:3], ok_v[:3])
+
+
+def test_null_handles_are_rejected(lib):
+    for fn, args in [(lib.pic_step, (None, 1)), (lib.pic_read_raw, (None, None, None, 0)),
+                     (lib.pic_read_history, (None, 0, 0, None)), (lib.pic_batch_step, (None, 1))]:
+        assert fn(*args) == P.PIC_EINVAL
+    d = P.pic_diag()
+    assert lib.pic_diagnostics(None, C.byref(d), None, None, 0) == P.PIC_EINVAL
+    assert lib.pic_destroy(None) == P.PIC_OK
+    assert lib.pic_batch_destroy(None) == P.PIC_OK
+
+
+@pytest.mark.parametrize("bad", [dict(max_runs=0), dict(ng_max=1), dict(ng_max=9000),
+                                 dict(graph_steps=-1), dict(hbm_budget=16)])
+def test_batch_create_validates_config(lib, bad):
+    cfg = dict(hbm_budget=1 << 30, ng_max=2048, max_runs=8, graph_steps=4)
+    cfg.update(bad)
+    with pytest.raises(P.PicError) as e:
+        P.pic_batch_create(**cfg)
+    assert e.value.status == P.PIC_EINVAL
+
+
+def test_missing_extension_fails_loudly(tmp_path, monkeypatch):
+    monkeypatch.setattr(P, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        P.load(str(tmp_path / "absent.so"))

@@ -1,0 +1,325 @@
+"""GPU parity of the HIP particle loop against the FP64 CPU oracle.
+
+All inputs are seeded and synthetic (paper_1108_1954_amd.inputs).  Integer
+work (the fixed-point charge deposit) must match bit for bit; floating-point
+results are held to tolerances derived from the arithmetic (see
+`push_tolerance`).  Every call goes through the C ABI.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1108_1954_amd import inputs as I
+from paper_1108_1954_amd import pic as P
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = 2.0 ** -24
+EPS64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    P.load()
+    torch.cuda.init()
+    yield
+
+
+def make_run(spec, precision=P.PIC_FP32, history=0, tile=0, x=None, v=None):
+    if x is None:
+        x, v = spec.particles()
+    p = P.make_params(spec.L, spec.ng, spec.np_, spec.dt, precision=precision,
+                      history_cap=history, tile=tile)
+    return P.Run(p, x, v), p
+
+
+def oracle_params(p):
+    return O.params(p.L, p.ng, p.np, dt=p.dt, qm=p.qm, rho0=p.rho0)
+
+
+def periodic_diff(a, b, period):
+    d = np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)
+    return d - period * np.round(d / period)
+
+
+def solve_tolerance(p, S):
+    """Rounding bound of the FP64 solve: the face field is a sum of ng terms
+    of size |rho - mean| dx in different orders on the two sides."""
+    rho = O.density_fixed(oracle_params(p), S)
+    dx = p.L / p.ng
+    return 8 * p.ng * EPS64 * dx * np.abs(rho - rho.mean()).sum() + 1e-300
+
+
+def push_tolerance(u_new, w_new, Ehat_max, ng, eps):
+    """One step in precision eps against the exact (FP64) step from the same
+    state and the same field:  the gather weight f has at most one rounding,
+    the stored table Ehat one, E_{j+1} - E_j and the FMA one each, so
+    |dEp| <= 6 eps max|Ehat|; the kick adds eps |w_new|; the drift eps |u_new|
+    and the wrap eps ng.  A factor 2 covers the FP64 side and conversions."""
+    dw = 2 * eps * (np.abs(w_new) + 6 * Ehat_max)
+    du = dw + 2 * eps * (np.abs(u_new) + ng)
+    return du, dw
+
+
+def check_deposit_exact(run, p, u):
+    S_gpu, _, _ = run.grid()
+    S_ora = O.deposit_fixed(p.ng, u.astype(np.float64))
+    np.testing.assert_array_equal(S_gpu, S_ora)
+    assert int(S_gpu.sum()) == p.np * 2 ** 32
+
+
+# ------------------------------------------------------------ single run ---
+
+@pytest.mark.parametrize("precision", [P.PIC_FP32, P.PIC_FP64])
+def test_initial_deposit_and_solve(precision):
+    spec = I.two_stream_small()
+    run, p = make_run(spec, precision)
+    with run:
+        u, _ = run.raw()
+        check_deposit_exact(run, p, u)
+        S, E, Eh = run.grid()
+        E_ora, _ = O.solve(oracle_params(p), O.density_fixed(oracle_params(p), S))
+        np.testing.assert_allclose(E, E_ora, rtol=0, atol=solve_tolerance(p, S))
+        ecoef = p.qm * p.dt ** 2 / (p.L / p.ng)
+        np.testing.assert_array_equal(Eh, (E * ecoef).astype(np.float32))
+        d, rho, Eg = run.diagnostics(grids=True)
+        assert d["step"] == 0 and d["charge_fixed_sum"] == p.np * 2 ** 32
+        assert abs(d["net_charge"]) < 1e-12
+        assert d["field"] == pytest.approx(O.field_energy(oracle_params(p), E_ora), rel=1e-12)
+        np.testing.assert_array_equal(Eg, E)
+
+
+@pytest.mark.parametrize("precision,np_,ng,tile", [
+    (P.PIC_FP32, 10_000, 64, 0),
+    (P.PIC_FP32, 300_001, 512, 0),        # many tiles, ragged tail (np mod 4 = 1)
+    (P.PIC_FP32, 70_003, 100, 1024),      # non power-of-two grid, explicit tile
+    (P.PIC_FP64, 300_001, 512, 0),
+    (P.PIC_FP64, 70_003, 8192, 256),      # largest grid, FP64 state (128 KiB LDS)
+    (P.PIC_FP32, 1, 2, 0),                # one particle, smallest grid
+    (P.PIC_FP32, 5, 3, 0),
+])
+def test_single_step_matches_oracle(precision, np_, ng, tile):
+    """From the same (downloaded) state and field, one GPU step agrees with the
+    FP64 oracle's step within the rounding bound, and the new deposit is bit
+    exact."""
+    spec = I.warm_two_stream_large(seed=11, np_=np_, ng=ng, nsteps=1, L=0.032 * ng)
+    run, p = make_run(spec, precision, history=4, tile=tile)
+    eps = EPS32 if precision == P.PIC_FP32 else EPS64
+    with run:
+        run.step(2)                                  # move away from the loader state
+        u0, w0 = run.raw()
+        S0, E0, Eh0 = run.grid()
+        op = oracle_params(p)
+        E_ora, _ = O.solve(op, O.density_fixed(op, S0))
+        np.testing.assert_allclose(E0, E_ora, rtol=0, atol=solve_tolerance(p, S0))
+        dx = p.L / p.ng
+        x0 = u0.astype(np.float64) * dx
+        v0 = w0.astype(np.float64) * dx / p.dt
+        Ep = O.gather(op, x0, E_ora)
+        x1, v1, _ = O.push(op, x0, v0, Ep)
+        run.step(1)
+        u1, w1 = run.raw()
+        u1o, w1o = x1 / dx, v1 * p.dt / dx
+        du, dw = push_tolerance(u1o, w1o, np.abs(Eh0).max(), p.ng, eps)
+        err_w = np.abs(w1.astype(np.float64) - w1o)
+        err_u = np.abs(periodic_diff(u1, u1o, p.ng))
+        assert np.all(err_w <= dw), f"max w error {err_w.max():.3g} vs bound {dw.max():.3g}"
+        assert np.all(err_u <= du), f"max u error {err_u.max():.3g} vs bound {du.max():.3g}"
+        assert np.all((u1 >= 0) & (u1 < p.ng))
+        check_deposit_exact(run, p, u1)
+        d, _, _ = run.diagnostics()
+        assert d["step"] == 3 and d["flags"] == 0
+
+
+def test_deposit_stays_bit_exact_over_many_steps():
+    spec = I.two_stream_small(np_=50_003)
+    run, p = make_run(spec, history=64)
+    with run:
+        for n in (1, 4, 15, 40):
+            run.step(n)
+            u, _ = run.raw()
+            check_deposit_exact(run, p, u)
+
+
+def test_edge_positions_deposit_exactly():
+    """Particles exactly on nodes, at 0, at cell edges and just below L."""
+    ng, L = 16, 16 * 0.032
+    dx = L / ng
+    xs = [0.0, dx / 2, dx, 1.5 * dx, L - dx / 2, L - 1e-12, 0.25 * dx, 7 * dx + 1e-15]
+    rng = np.random.default_rng(3)
+    x = np.concatenate([xs, rng.uniform(0, L, 1000 - len(xs))])
+    v = np.zeros_like(x)
+    p = P.make_params(L, ng, x.size, 0.1)
+    with P.Run(p, x, v) as run:
+        u, _ = run.raw()
+        check_deposit_exact(run, p, u)
+        run.step(3)
+        u, _ = run.raw()
+        check_deposit_exact(run, p, u)
+
+
+def test_graph_replay_is_bit_identical_to_plain_launches():
+    spec = I.two_stream_small(np_=40_000)
+    x, v = spec.particles()
+    a, p = make_run(spec, history=64, x=x, v=v)
+    b, _ = make_run(spec, history=64, x=x, v=v)
+    with a, b:
+        a.step(37)
+        b.step(37, graph_steps=8)                    # 4 graph replays + 5 plain launches
+        ua, wa = a.raw()
+        ub, wb = b.raw()
+        np.testing.assert_array_equal(ua, ub)
+        np.testing.assert_array_equal(wa, wb)
+        np.testing.assert_array_equal(a.history(), b.history())
+
+
+# ----------------------------------------------------- runs vs the oracle ---
+
+def test_two_stream_history_against_fp64_oracle():
+    """Two-stream run (Ng=64, Np=10,000, 200 steps): W_E history of the
+    FP32/fixed-point engine vs the FP64 oracle from the same FP64 inputs."""
+    spec = I.two_stream_small()
+    x, v = spec.particles()
+    run, p = make_run(spec, history=spec.nsteps, x=x, v=v)
+    with run:
+        run.step(spec.nsteps)
+        h = run.history()
+    ref = O.run(oracle_params(p), x, v, spec.nsteps, mode=O.DEPOSIT_FIXED)["hist"]
+    we, we_o = h[:, 1], ref[:, 1]
+    lin = slice(0, 100)                                   # linear phase, t < 10
+    err_lin = np.abs(we[lin] - we_o[lin]).max() / we_o[lin].max()
+    assert err_lin < 1e-3, err_lin
+    # momentum conserved to FP32 rounding; energy as well as the oracle's
+    m = O.particle_mass(oracle_params(p))
+    assert np.abs(h[:, 2] - h[0, 2]).max() < 1e-5 * m * np.abs(v).sum()
+    et = h[:, 0] + h[:, 1]
+    assert np.abs(et[:100] - et[0]).max() / et[0] < 3e-4
+
+
+def test_cold_plasma_frequency_on_gpu():
+    s = I.cold_plasma(nsteps=400)
+    run, p = make_run(s, history=s.nsteps)
+    with run:
+        run.step(s.nsteps)
+        we = run.history()[:, 1]
+    # W_E oscillates at twice the plasma frequency; locate its minima to
+    # sub-step accuracy with a parabola through the three nearest samples
+    mins = []
+    for i in range(1, len(we) - 1):
+        if we[i] < we[i - 1] and we[i] <= we[i + 1]:
+            den = we[i - 1] - 2 * we[i] + we[i + 1]
+            mins.append((i + 0.5 * (we[i - 1] - we[i + 1]) / den) * s.dt)
+    omega = math.pi * (len(mins) - 1) / (mins[-1] - mins[0])
+    from test_oracle_pins import predicted_cold_plasma_frequency
+    pred = predicted_cold_plasma_frequency(s.L, s.ng, s.dt, 2 * math.pi / s.L)
+    assert len(mins) >= 10
+    assert abs(omega - pred) < 1e-3, (omega, pred)
+
+
+def test_two_stream_growth_rate_on_gpu():
+    s = I.quiet_two_stream(nsteps=300)
+    run, p = make_run(s, history=s.nsteps)
+    with run:
+        run.step(s.nsteps)
+        we = run.history()[:, 1]
+    from test_oracle_pins import two_stream_growth_rate, _mode1
+    g_th = two_stream_growth_rate(2 * math.pi / s.L, 0.2)
+    t = np.arange(s.nsteps) * s.dt
+    # the fit window of the oracle's gate: 12..4 time units before the mode-1
+    # amplitude reaches 1% of ng in the oracle's own run of the same set-up
+    x, v = s.particles()
+    ref = O.run(oracle_params(p), x, v, s.nsteps, keep_E=True)
+    amp_o = np.abs(_mode1(ref["E_hist"])) * s.ng
+    t01 = t[int(np.argmax(amp_o > 0.01 * s.ng))]
+    m = (t >= t01 - 12) & (t <= t01 - 4)
+    gamma = np.polyfit(t[m], 0.5 * np.log(we[m]), 1)[0]
+    assert abs(gamma / g_th - 1) < 0.02, gamma
+
+
+# ------------------------------------------------------------- batching ---
+
+def small_ensemble(n, seed=3):
+    runs = I.ensemble(nruns=n, seed=seed, nsteps=30, np_scale=0.02)
+    return runs
+
+
+def test_batched_runs_equal_the_same_runs_alone():
+    specs = small_ensemble(6)
+    parts = [s.particles() for s in specs]
+    alone = []
+    for s, (x, v) in zip(specs, parts):
+        r, p = make_run(s, history=s.nsteps, x=x, v=v)
+        with r:
+            r.step(s.nsteps)
+            alone.append((r.raw(), r.grid(), r.history()))
+    b = P.pic_batch_create(1 << 30, 2048, max_runs=16, graph_steps=4, stream=P.current_stream())
+    try:
+        ids = []
+        for s, (x, v) in zip(specs, parts):
+            p = P.make_params(s.L, s.ng, s.np_, s.dt, history_cap=s.nsteps)
+            ids.append(P.pic_batch_admit(b, p, x, v, s.nsteps))
+        P.pic_batch_step(b, 100)                       # more than needed: runs stop at their own count
+        for rid, s, (raw, grid, hist) in zip(ids, specs, alone):
+            view = P.pic_batch_run(b, rid)
+            u, w = P.pic_read_raw(view, s.np_)
+            np.testing.assert_array_equal(u, raw[0])
+            np.testing.assert_array_equal(w, raw[1])
+            S, E, _ = P.pic_read_grid(view, s.ng)
+            np.testing.assert_array_equal(S, grid[0])
+            np.testing.assert_array_equal(E, grid[1])
+            np.testing.assert_array_equal(P.pic_read_history(view, 0, s.nsteps), hist)
+            d, _, _ = P.pic_diagnostics(view)
+            assert d["step"] == s.nsteps
+        done = P.pic_batch_poll(b)
+        assert sorted(done) == sorted(ids)
+    finally:
+        P.pic_batch_destroy(b)
+
+
+def test_admission_under_a_small_budget_and_release():
+    """A budget that holds only some runs: admission reports EBUDGET, runs are
+    admitted as others release, and every result equals the run alone."""
+    specs = small_ensemble(5, seed=8)
+    parts = [s.particles() for s in specs]
+    foot = [P.pic_footprint(P.make_params(s.L, s.ng, s.np_, s.dt, history_cap=s.nsteps)) for s in specs]
+    budget = int(max(foot) * 1.5)
+    b = P.pic_batch_create(budget, 2048, max_runs=8, graph_steps=2, stream=P.current_stream())
+    results = {}
+    try:
+        pending = list(range(len(specs)))
+        active = {}
+        refused = 0
+        while pending or active:
+            still = []
+            for k in pending:
+                s = specs[k]
+                p = P.make_params(s.L, s.ng, s.np_, s.dt, history_cap=s.nsteps)
+                try:
+                    active[P.pic_batch_admit(b, p, *parts[k], s.nsteps)] = k
+                except P.PicBudget:
+                    refused += 1
+                    still.append(k)
+            pending = still
+            P.pic_batch_step(b, 7)
+            import torch
+            torch.cuda.synchronize()
+            for rid in P.pic_batch_poll(b):
+                k = active.pop(rid)
+                view = P.pic_batch_run(b, rid)
+                results[k] = P.pic_read_raw(view, specs[k].np_)
+                P.pic_batch_release(b, rid)
+        assert refused > 0
+        assert P.pic_batch_usage(b)[0] == 0
+    finally:
+        P.pic_batch_destroy(b)
+    for k, s in enumerate(specs):
+        r, _ = make_run(s, x=parts[k][0], v=parts[k][1])
+        with r:
+            r.step(s.nsteps)
+            u, w = r.raw()
+        np.testing.assert_array_equal(results[k][0], u)
+        np.testing.assert_array_equal(results[k][1], w)
