@@ -9,13 +9,13 @@ namespace pic1d {
 
 constexpr int kMaxNg = 8192;
 constexpr int kHistCols = 4;
-constexpr int kPartCols = 4;     // per tile: sum w_old^2, sum w_new^2, sum w_new, unused
+constexpr int kPartCols = 2;     // per tile: sum w_new^2, sum w_new
 constexpr int kWave = 64;
 
 // Device-resident descriptor of one run.  Lives in device memory; the
 // kernels update step/counter/flags and the "now" diagnostics.
 struct RunDev {
-    void *u, *w;                 // state: u = x/dx in [0, ng), w = v dt/dx
+    void *u, *w;                 // state: s = x/dx + 1/2 in [1/2, ng + 1/2), w = v dt/dx
     void *u_alt, *w_alt;         // cell-sort destination (ping-pong), may be null
     unsigned long long *S;       // [ng] fixed-point charge sums, zero between steps
     unsigned long long *S_last;  // [ng] copy of S from the latest solve
@@ -33,7 +33,7 @@ struct RunDev {
     int32_t tile;                // particles per tile (multiple of 256)
     int32_t ntiles;
     int32_t precision;           // 0 = FP32 state, 1 = FP64 state
-    uint32_t counter;            // tiles finished in the current pass
+    uint32_t pad0_;
     uint32_t flags;              // PIC_FLAG_* bits
     double dx;
     double qfac;                 // Q / (dx 2^32): density per unit of S
@@ -48,32 +48,45 @@ struct RunDev {
     int32_t pad_;
 };
 
-// One unit of schedule: tiles [tile_begin, tile_end) of run `run`.
+// One unit of schedule: tiles [tile_begin, tile_end) of run `run`, which is
+// chunk `chunk` of the run's `nchunks` chunks in this launch.
 struct WorkItem {
     int32_t run;
     int32_t tile_begin;
     int32_t tile_end;
+    int32_t chunk;
+    int32_t nchunks;
     int32_t pad_;
 };
 
-// Kernel launchers (pic_kernels.hip).  All enqueue on `stream` and return
-// the launch status.
+// Launch shape of the step kernel (chosen per run by the autotuner):
+// threads per workgroup and particle vectors per lane per iteration.
+struct LaunchShape {
+    int block = 512;
+    int unroll = 2;
+};
+
+// Kernel launchers (pic_kernels.hip).  launch_step enqueues one step on
+// `stream` as two launches: the particle pass, then the field solve.
 //   items == nullptr: single run `runs[0]`, tiles split evenly over `grid`
 //   workgroups.  Otherwise workgroup b processes items[wg_begin[b] ..
 //   wg_begin[b+1]).
+//   The solve launch has nsolve workgroups; workgroup b solves runs[b]
+//   (idle and finished runs return at once).
 //   prologue != 0: deposit + solve only (creation), no push.
 hipError_t launch_step(RunDev *runs, const WorkItem *items, const int32_t *wg_begin,
-                       int grid, int block, int ng_lds, int precision, int prologue,
-                       hipStream_t stream);
+                       int grid, const LaunchShape &shape, int ng_lds, int precision, int prologue,
+                       int nsolve, hipStream_t stream);
 
-// Allow the step kernels of this block size/precision the LDS they need
-// (called once before the first launch and before any graph capture).
-hipError_t step_prepare(int block, int precision);
+// Allow the step kernels of this shape/precision the LDS they need (called
+// once before the first launch and before any graph capture).
+hipError_t step_prepare(const LaunchShape &shape, int precision);
 
 // Largest resident workgroups per CU for the step kernel.
-int step_occupancy(int block, int ng_lds, int precision);
+int step_occupancy(const LaunchShape &shape, int ng_lds, int precision);
 
-// Dynamic LDS of one workgroup: the int64 grid plus the gather table.
+// Dynamic LDS of one workgroup: the int64 grid plus the gather table, each
+// with two ghost nodes.
 size_t step_lds_bytes(int precision, int ng_lds);
 
 }  // namespace pic1d

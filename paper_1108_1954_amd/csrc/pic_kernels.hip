@@ -13,7 +13,14 @@
 // domain; the grid reduction replaces the paper's ghost-cell exchange and the
 // solve replaces its distributed CG.  All per-run reductions use fixed
 // orders that depend only on the run's (np, ng, tile), never on the launch
-// shape, so a run gives identical results alone or batched with others.
+// shape (block size, unroll, grid, batch membership), so a run gives
+// bit-identical results alone or batched with others.
+//
+// Stored position: s = x/dx + 1/2 in [1/2, ng + 1/2).  Then t = s - 1 =
+// x/dx - 1/2 (the position measured from node 0, nodes at (g + 1/2) dx) is
+// exact, and so are j = floor(t) and the fraction f = t - j; in FP32,
+// f 2^32 is an integer, so the fixed-point deposit needs no 64-bit
+// arithmetic.  The host reads positions back as s - 1/2 (also exact).
 #include "pic_internal.h"
 
 namespace pic1d {
@@ -29,6 +36,8 @@ template <typename T> struct Vec;
 template <> struct Vec<float> { using type = f32x4; static constexpr int n = 4; };
 template <> struct Vec<double> { using type = f64x2; static constexpr int n = 2; };
 
+constexpr int kSolveThreads = 256;   // threads that compute in the solve
+
 // Streaming accesses to particle arrays: global address space, non-temporal
 // (each particle is touched once per step).
 template <typename V>
@@ -40,37 +49,13 @@ __device__ __forceinline__ void store_stream(void *p, V v) {
     __builtin_nontemporal_store(v, (GLOBAL_AS V *)p);
 }
 
-template <typename T>
-__device__ __forceinline__ T fma_t(T a, T b, T c);
-template <> __device__ __forceinline__ float fma_t<float>(float a, float b, float c) {
-    return __builtin_fmaf(a, b, c);
-}
-template <> __device__ __forceinline__ double fma_t<double>(double a, double b, double c) {
-    return __builtin_fma(a, b, c);
-}
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Fixed-point index of a position u = x/dx (the exact deposit rule): with
-// U = floor(u 2^32) and U' = U - 2^31 (the half-cell shift from cell edges to
-// nodes at (g + 1/2) dx), the left node is j = floor(U' / 2^32) and the
-// 32-bit fraction is F = U' - j 2^32.  Evaluated without 64-bit integers:
-//   u >= 1/2: t = u - 1/2 is exact (1/2 is a multiple of ulp(u)), so is
-//             t - floor(t), and F = (t - floor(t)) 2^32 truncated;
-//   u <  1/2: j = -1 and F = floor(u 2^32) + 2^31 (u 2^32 is exact).
-// Also returns the gather weight f of node j+1 (= F 2^-32 up to rounding).
-// j is clamped to [-1, ng-1] so that a corrupt position cannot index outside
-// the grid.
-template <typename T>
-__device__ __forceinline__ void fixed_index(T u, int ng, int &j, uint32_t &F, T &f) {
-    const T t = u - T(0.5);
-    const T jf = __builtin_floor(t);
-    const T fr = t - jf;
-    const bool upper = u >= T(0.5);
-    const uint32_t F_hi = (uint32_t)(fr * T(4294967296.0));
-    const uint32_t F_lo = (uint32_t)(u * T(4294967296.0)) + 0x80000000u;
-    F = upper ? F_hi : F_lo;
-    j = upper ? min((int)jf, ng - 1) : -1;
-    f = upper ? fr : u + T(0.5);
-}
+// 32-bit fraction F = floor(f 2^32) of a cell fraction f in [0, 1).
+// FP32: f is a multiple of 2^-24, so f 2^32 is an exact integer.
+__device__ __forceinline__ uint32_t frac32(float f) { return (uint32_t)(f * 4294967296.0f); }
+__device__ __forceinline__ uint32_t frac32(double f) { return (uint32_t)(f * 4294967296.0); }
 
 template <typename T> __device__ __forceinline__ const T *gather_table(const RunDev *R);
 template <> __device__ __forceinline__ const float *gather_table<float>(const RunDev *R) {
@@ -80,53 +65,65 @@ template <> __device__ __forceinline__ const double *gather_table<double>(const 
     return R->Ehat64;
 }
 
-template <typename T>
-__device__ __forceinline__ bool inside(T u, T ngf) { return u >= T(0) && u < ngf; }
+// Per-particle stages.  Conventions:
+//   s, w : stored position (x/dx + 1/2) and velocity w = v dt/dx
+//   Et   : gather table in LDS, Et[g+1] = E_g scaled to the change of w per
+//          step, with ghosts Et[0] = E_{ng-1} and Et[ng+1] = E_0
+//   Sl   : workgroup-private int64 grid in LDS, node g at Sl[g+1], ghosts
+//          Sl[0] (node -1 = ng-1) and Sl[ng+1] (node ng = 0)
+// Node indices are clamped to [-1, ng-1] so no value of s can address
+// outside the tables.
 
-// One particle through gather, kick, drift, wrap and deposit.
-// Es: gather table in LDS (E scaled to the change of w per step).
-// Sl: workgroup-private int64 grid in LDS.
-// a0, a1, a2: running sums of w_old^2, w_new^2, w_new for the diagnostics.
-template <typename T, bool PUSH>
-__device__ __forceinline__ void particle(T &u, T &w, const T *Es, unsigned long long *Sl, int ng,
-                                         T ngf, double &a0, double &a1, double &a2,
-                                         uint32_t &flags) {
-    int j;
-    uint32_t F;
-    T f;
-    if (PUSH) {
-        fixed_index(u, ng, j, F, f);
-        const int jl = j < 0 ? ng - 1 : j;
-        const int jr = j + 1 >= ng ? 0 : j + 1;
-        const T El = Es[jl];
-        const T Ep = fma_t<T>(f, Es[jr] - El, El);    // (1-f) E_j + f E_{j+1}
-        const double wo = (double)w;
-        a0 = __builtin_fma(wo, wo, a0);
-        w = w + Ep;                                   // v^{n+1/2} = v^{n-1/2} + qm E dt
-        T un = u + w;                                 // x^{n+1} = x^n + v^{n+1/2} dt
-        un = un + (un < T(0) ? ngf : (un >= ngf ? -ngf : T(0)));
-        if (!inside(un, ngf)) {                       // rare: rounding to ng, |w| >= ng, NaN
-            if (un == ngf) {
-                un = T(0);
-            } else if (!__builtin_isfinite(un)) {
-                un = T(0);
-                flags |= 1u;
-            } else {
-                un = un - ngf * __builtin_floor(un / ngf);
-                if (!inside(un, ngf)) un = T(0);
-                flags |= 2u;
-            }
+// Field at the particle from the two nearest nodes (Sec. 2.3):
+// (1-f) E_j + f E_{j+1} with j = floor(x/dx - 1/2), f the fraction.
+template <typename T>
+__device__ __forceinline__ T gather(T s, const T *Et, int ng) {
+    const T t = s - T(1);
+    const T jf = __builtin_floor(t);
+    const T f = t - jf;
+    const int j = min(max((int)jf, -1), ng - 1);
+    const T El = Et[j + 1];
+    const T Er = Et[j + 2];
+    return fma_t(f, Er - El, El);
+}
+
+// Leapfrog kick and drift with periodic wrap (Sec. 2.1).
+template <typename T>
+__device__ __forceinline__ void push(T &s, T &w, T Ep, T ngf, T hi, uint32_t &flags) {
+    w = w + Ep;                                   // v^{n+1/2} = v^{n-1/2} + qm E dt
+    T sn = s + w;                                 // x^{n+1} = x^n + v^{n+1/2} dt
+    sn = sn + (sn < T(0.5) ? ngf : (sn >= hi ? -ngf : T(0)));
+    if (!(sn >= T(0.5) && sn < hi)) {             // rare: rounding to the end, |w| >= ng, NaN
+        if (sn == hi) {
+            sn = T(0.5);
+        } else if (!__builtin_isfinite(sn)) {
+            sn = T(0.5);
+            flags |= 1u;
+        } else {
+            sn = sn - ngf * __builtin_floor((sn - T(0.5)) / ngf);
+            if (!(sn >= T(0.5) && sn < hi)) sn = T(0.5);
+            flags |= 2u;
         }
-        u = un;
     }
+    s = sn;
+}
+
+// Exact fixed-point charge deposit (Sec. 2.3 weights): with
+// U' = floor((x/dx - 1/2) 2^32) = j 2^32 + F, node j gets 2^32 - F and node
+// j+1 gets F.  Also accumulates the diagnostics sums w^2 and w.
+template <typename T>
+__device__ __forceinline__ void deposit(T s, T w, unsigned long long *Sl, int ng, double &a1,
+                                        double &a2) {
     const double wn = (double)w;
     a1 = __builtin_fma(wn, wn, a1);
     a2 += wn;
-    fixed_index(u, ng, j, F, f);
-    const int jl = j < 0 ? ng - 1 : j;
-    const int jr = j + 1 >= ng ? 0 : j + 1;
-    atomicAdd(&Sl[jl], (1ull << 32) - (unsigned long long)F);
-    atomicAdd(&Sl[jr], (unsigned long long)F);
+    const T t = s - T(1);
+    const T jf = __builtin_floor(t);
+    const uint32_t F = frac32(t - jf);
+    const int j = min(max((int)jf, -1), ng - 1);
+    unsigned long long *p = Sl + (j + 1);
+    atomicAdd(p, (1ull << 32) - (unsigned long long)F);
+    atomicAdd(p + 1, (unsigned long long)F);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -141,22 +138,22 @@ __device__ __forceinline__ long long wave_sum(long long v) {
     return v;
 }
 
-// Block-wide sums in a fixed order (butterfly inside each wavefront, then the
-// wavefront totals in index order); every thread gets the same value.
-template <int BLOCK, typename V>
-__device__ V block_sum(V v, V *red) {
+// Sum over the first kSolveThreads threads in a fixed order (butterfly inside
+// each wavefront, then wavefront totals in index order); every thread of the
+// block gets the value.  All threads of the block must call it.
+template <typename V>
+__device__ V solve_sum(V v, V *red) {
     v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    if ((threadIdx.x & 63) == 0 && threadIdx.x < kSolveThreads) red[threadIdx.x >> 6] = v;
     __syncthreads();
     V s = 0;
-    for (int k = 0; k < BLOCK / 64; ++k) s += red[k];
+    for (int k = 0; k < kSolveThreads / 64; ++k) s += red[k];
     __syncthreads();
     return s;
 }
 
-// Exclusive prefix sum over threads in index order.
-template <int BLOCK>
-__device__ double block_exclusive_scan(double v, double *red) {
+// Exclusive prefix sum over the first kSolveThreads threads in index order.
+__device__ double solve_exclusive_scan(double v, double *red) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double inc = v;
 #pragma unroll
@@ -166,112 +163,206 @@ __device__ double block_exclusive_scan(double v, double *red) {
     }
     double exc = __shfl_up(inc, 1);
     if (lane == 0) exc = 0.0;
-    if (lane == 63) red[wv] = inc;
+    if (lane == 63 && threadIdx.x < kSolveThreads) red[wv] = inc;
     __syncthreads();
     double off = 0.0;
-    for (int k = 0; k < wv; ++k) off += red[k];
+    for (int k = 0; k < wv && k < kSolveThreads / 64; ++k) off += red[k];
     __syncthreads();
     return off + exc;
 }
 
-// Periodic Poisson solve of one run by one workgroup (Sec. 2.2).
+// Periodic Poisson solve of one run by one workgroup (Sec. 2.2), computed by
+// its first kSolveThreads threads whatever the block size.
 // The face field F_{g+1/2} = -(phi_{g+1} - phi_g)/dx satisfies
 // F_{g+1/2} - F_{g-1/2} = (rho_g - mean rho) dx, so it is a prefix sum;
 // periodicity of phi sets sum_g F_{g+1/2} = 0; the central-difference node
-// field is E_g = (F_{g-1/2} + F_{g+1/2}) / 2.  D: LDS scratch of ng doubles
-// (all zero on entry and on return).
-template <int BLOCK>
+// field is E_g = (F_{g-1/2} + F_{g+1/2}) / 2.  D: LDS scratch of ng doubles.
 __device__ __noinline__ void solve_run(RunDev *R, double *D, double *red, long long *redi,
                                        bool prologue) {
     const int ng = R->ng;
     const int tid = threadIdx.x;
+    const bool worker = tid < kSolveThreads;
     unsigned long long *S = R->S;
     unsigned long long *S_last = R->S_last;
+    // Plain loads: this runs in the launch after the deposit, so the kernel
+    // boundary orders them after every workgroup's merge into S and its tile
+    // partials.
+    // Loads are issued in batches of kBatch so that many are in flight; the
+    // sums keep the strided order g = tid, tid + 256, ...
+    constexpr int kBatch = 16;
     long long tot = 0;
-    for (int g = tid; g < ng; g += BLOCK) {
-        unsigned long long s = __hip_atomic_load(S + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        S[g] = 0ull;
-        S_last[g] = s;
-        tot += (long long)s;
-        D[g] = (double)s;
+    if (worker) {
+        for (int g0 = tid; g0 < ng; g0 += kSolveThreads * kBatch) {
+            unsigned long long sv[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int g = g0 + k * kSolveThreads;
+                sv[k] = g < ng ? S[g] : 0ull;
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int g = g0 + k * kSolveThreads;
+                if (g < ng) {
+                    S[g] = 0ull;
+                    S_last[g] = sv[k];
+                    tot += (long long)sv[k];
+                    D[g] = (double)sv[k];
+                }
+            }
+        }
     }
-    tot = block_sum<BLOCK>(tot, redi);           // exact: sum_g S_g
+    tot = solve_sum(tot, redi);                   // exact: sum_g S_g
     const double meanS = (double)tot / (double)ng;
-    const double scale = R->qfac * R->dx;        // face-field change per unit of S
-    const int seg = (ng + BLOCK - 1) / BLOCK;
-    const int g0 = min(tid * seg, ng), g1 = min(g0 + seg, ng);
+    const double scale = R->qfac * R->dx;         // face-field change per unit of S
+    const int seg = (ng + kSolveThreads - 1) / kSolveThreads;
+    const int g0 = worker ? min(tid * seg, ng) : ng, g1 = min(g0 + seg, ng);
     double acc = 0.0;
     for (int g = g0; g < g1; ++g) {
         acc += (D[g] - meanS) * scale;
         D[g] = acc;
     }
-    const double off = block_exclusive_scan<BLOCK>(acc, red);
+    const double off = solve_exclusive_scan(acc, red);
     double csum = 0.0;
     for (int g = g0; g < g1; ++g) {
         double fv = D[g] + off;
         D[g] = fv;
         csum += fv;
     }
-    const double C = -block_sum<BLOCK>(csum, red) / (double)ng;   // syncs: D complete
+    const double C = -solve_sum(csum, red) / (double)ng;   // syncs: D complete
     const double ecoef = R->ecoef;
     float *Ehat = R->Ehat;
     double *Ehat64 = R->Ehat64;
     double *E64 = R->E64;
     double we = 0.0;
-    for (int g = tid; g < ng; g += BLOCK) {
-        double left = D[g == 0 ? ng - 1 : g - 1];
-        double E = 0.5 * (left + D[g]) + C;
-        E64[g] = E;
-        double eh = E * ecoef;
-        Ehat[g] = (float)eh;
-        if (Ehat64) Ehat64[g] = eh;
-        we += E * E;
+    if (worker) {
+        for (int g = tid; g < ng; g += kSolveThreads) {
+            double left = D[g == 0 ? ng - 1 : g - 1];
+            double E = 0.5 * (left + D[g]) + C;
+            E64[g] = E;
+            double eh = E * ecoef;
+            Ehat[g] = (float)eh;
+            if (Ehat64) Ehat64[g] = eh;
+            we += E * E;
+        }
     }
-    we = 0.5 * R->dx * block_sum<BLOCK>(we, red);
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    we = 0.5 * R->dx * solve_sum(we, red);
+    double a1 = 0.0, a2 = 0.0;
     const double *part = R->tile_part;
     const int ntiles = R->ntiles;
-    for (int t = tid; t < ntiles; t += BLOCK) {
-        a0 += __hip_atomic_load(part + kPartCols * t + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a1 += __hip_atomic_load(part + kPartCols * t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a2 += __hip_atomic_load(part + kPartCols * t + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (worker) {
+        for (int t0 = tid; t0 < ntiles; t0 += kSolveThreads * kBatch) {
+            f64x2 pv[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int t = t0 + k * kSolveThreads;
+                pv[k] = t < ntiles ? *reinterpret_cast<const f64x2 *>(part + kPartCols * t) : f64x2{0.0, 0.0};
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                a1 += pv[k].x;
+                a2 += pv[k].y;
+            }
+        }
     }
-    a0 = block_sum<BLOCK>(a0, red);
-    a1 = block_sum<BLOCK>(a1, red);
-    a2 = block_sum<BLOCK>(a2, red);
+    a1 = solve_sum(a1, red);
+    a2 = solve_sum(a2, red);
     if (tid == 0) {
         const double kc = R->kcoef, pc = R->pcoef;
+        const double k_new = kc * a1;
         if (!prologue) {
             const int64_t n = R->step;
             if (n < R->hist_cap) {
                 double *row = R->hist + (size_t)kHistCols * (size_t)n;
-                row[0] = 0.5 * kc * (a0 + a1);   // KE^n, time-centred
-                row[1] = R->field_now;           // W_E^n of the field this step gathered
-                row[2] = pc * a2;                // P^{n+1/2}
-                row[3] = kc * a1;                // K^{n+1/2}
+                row[0] = 0.5 * (R->kinetic_now + k_new);   // KE^n, time-centred
+                row[1] = R->field_now;                     // W_E^n of the gathered field
+                row[2] = pc * a2;                          // P^{n+1/2}
+                row[3] = k_new;                            // K^{n+1/2}
             }
             R->step = n + 1;
         }
-        R->kinetic_now = kc * a1;
+        R->kinetic_now = k_new;
         R->momentum_now = pc * a2;
         R->field_now = we;
         R->charge_now = (int64_t)tot;
-        R->counter = 0u;
     }
-    for (int g = tid; g < ng; g += BLOCK) D[g] = 0.0;
-    __syncthreads();
+}
+
+// Issue the loads of one block: UNROLL vectors of VEC particles per lane,
+// lane-contiguous so each load instruction covers 64*VEC particles.
+template <typename V, int VEC, int UNROLL>
+__device__ __forceinline__ void load_block(const void *U, const void *W, int64_t base, int lane,
+                                           V (&u)[UNROLL], V (&w)[UNROLL]) {
+    using T = decltype(u[0][0] + 0);
+#pragma unroll
+    for (int k = 0; k < UNROLL; ++k) {
+        const int64_t i = base + (int64_t)(k * 64 + lane) * VEC;
+        u[k] = load_stream<V>((const T *)U + i);
+        w[k] = load_stream<V>((const T *)W + i);
+    }
+}
+
+// Push and deposit one loaded block, then store it back.  All gathers of the
+// block are issued first (one LDS wait per block), then the pushes, deposits
+// and stores; the accumulation order per lane is the particle order.
+template <typename T, typename V, int VEC, int UNROLL, bool PUSH>
+__device__ __forceinline__ void run_block(void *U, void *W, int64_t base, int lane, V (&u)[UNROLL],
+                                          V (&w)[UNROLL], const T *Et, unsigned long long *Sl, int ng,
+                                          T ngf, T hi, double &a1, double &a2, uint32_t &flags) {
+    if (PUSH) {
+        T Ep[UNROLL][VEC];
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) Ep[k][e] = gather(u[k][e], Et, ng);
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                T sv = u[k][e], wv = w[k][e];
+                push(sv, wv, Ep[k][e], ngf, hi, flags);
+                u[k][e] = sv;
+                w[k][e] = wv;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < UNROLL; ++k)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) deposit(u[k][e], w[k][e], Sl, ng, a1, a2);
+    if (PUSH) {
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) {
+            const int64_t i = base + (int64_t)(k * 64 + lane) * VEC;
+            store_stream<V>((T *)U + i, u[k]);
+            store_stream<V>((T *)W + i, w[k]);
+        }
+    }
+}
+
+// The same stages for one particle (ragged tile ends).
+template <typename T, bool PUSH>
+__device__ __forceinline__ void run_one(T *U, T *W, int64_t q, const T *Et, unsigned long long *Sl,
+                                        int ng, T ngf, T hi, double &a1, double &a2, uint32_t &flags) {
+    T sv = U[q], wv = W[q];
+    if (PUSH) push(sv, wv, gather(sv, Et, ng), ngf, hi, flags);
+    deposit(sv, wv, Sl, ng, a1, a2);
+    if (PUSH) {
+        U[q] = sv;
+        W[q] = wv;
+    }
 }
 
 // All tiles [tb, te) of run R: wavefront k of the block takes tiles
-// tb + k, tb + k + nwaves, ...; each lane streams VEC particles per
-// iteration, with the next iteration's loads issued before the current
-// particles are processed.
-template <typename T, int BLOCK, bool PUSH>
-__device__ void process_chunk(RunDev *R, int tb, int te, bool load_table, unsigned long long *Sl,
-                              T *Es, double *red, long long *redi, int *s_last) {
+// tb + k, tb + k + nwaves, ...  Each lane handles UNROLL vectors of VEC
+// particles per iteration, all loads issued before any compute.  A lane's
+// particles are accumulated in index order for every UNROLL, so the tile
+// partial sums do not depend on it.
+template <typename T, int BLOCK, int UNROLL, bool PUSH>
+__device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_table,
+                              unsigned long long *Sl, T *Et) {
     using V = typename Vec<T>::type;
     constexpr int VEC = Vec<T>::n;
-    constexpr int STRIDE = 64 * VEC;
+    constexpr int PER = 64 * VEC * UNROLL;
     const int ng = R->ng;
     const int64_t np = R->np;
     const int tile = R->tile;
@@ -279,102 +370,98 @@ __device__ void process_chunk(RunDev *R, int tb, int te, bool load_table, unsign
     T *W = (T *)R->w;
     double *part = R->tile_part;
     const T ngf = (T)ng;
+    const T hi = ngf + T(0.5);
     if (PUSH && load_table) {
         const T *tab = gather_table<T>(R);
-        for (int g = threadIdx.x; g < ng; g += BLOCK) Es[g] = tab[g];
+        for (int g = threadIdx.x; g < ng; g += BLOCK) Et[g + 1] = tab[g];
+        if (threadIdx.x == 0) {
+            Et[0] = tab[ng - 1];
+            Et[ng + 1] = tab[0];
+        }
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t flags = 0;
-    for (int t = tb + wave; t < te; t += BLOCK / 64) {
+    for (int t = __builtin_amdgcn_readfirstlane(tb + wave); t < te; t += BLOCK / 64) {
         const int64_t p0 = (int64_t)t * tile;
         const int64_t p1 = min(p0 + (int64_t)tile, np);
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        int64_t i = p0 + (int64_t)lane * VEC;
-        V un, wn;
-        if (i + VEC <= p1) {
-            un = load_stream<V>(U + i);
-            wn = load_stream<V>(W + i);
+        double a1 = 0.0, a2 = 0.0;
+        // Full blocks of PER particles, software-pipelined over two register
+        // sets: the loads of the next block are issued before the current
+        // block is processed and stored, so a wave waits for one load latency
+        // per block and never for its own stores.
+        const int64_t nb = (p1 - p0) / PER;
+        const int64_t last = p0 + (nb - 1) * PER;    // base of the last full block
+        V au[UNROLL], aw[UNROLL], bu[UNROLL], bw[UNROLL];
+        if (nb > 0) load_block<V, VEC, UNROLL>(U, W, p0, lane, au, aw);
+        // Pairs of blocks with unconditional loads (the load after the last
+        // pair re-reads the last block, in bounds), so every iteration issues
+        // the same memory operations and a wave waits only for the loads it
+        // issued one block earlier.
+        const int64_t npairs = nb / 2;
+        for (int64_t q = 0; q < npairs; ++q) {
+            const int64_t base = p0 + 2 * q * PER;
+            load_block<V, VEC, UNROLL>(U, W, base + PER, lane, bu, bw);
+            run_block<T, V, VEC, UNROLL, PUSH>(U, W, base, lane, au, aw, Et, Sl, ng, ngf, hi, a1, a2, flags);
+            load_block<V, VEC, UNROLL>(U, W, min(base + 2 * PER, last), lane, au, aw);
+            run_block<T, V, VEC, UNROLL, PUSH>(U, W, base + PER, lane, bu, bw, Et, Sl, ng, ngf, hi, a1, a2,
+                                               flags);
         }
-        for (; i < p1; i += STRIDE) {
-            if (i + VEC <= p1) {
-                V uu = un, ww = wn;
-                const int64_t inext = i + STRIDE;
-                if (inext + VEC <= p1) {
-                    un = load_stream<V>(U + inext);
-                    wn = load_stream<V>(W + inext);
-                }
-#pragma unroll
-                for (int k = 0; k < VEC; ++k) {
-                    T uk = uu[k], wk = ww[k];
-                    particle<T, PUSH>(uk, wk, Es, Sl, ng, ngf, a0, a1, a2, flags);
-                    uu[k] = uk;
-                    ww[k] = wk;
-                }
-                if (PUSH) {
-                    store_stream<V>(U + i, uu);
-                    store_stream<V>(W + i, ww);
-                }
-            } else {
-                for (int64_t q = i; q < p1; ++q) {
-                    T uu = U[q], ww = W[q];
-                    particle<T, PUSH>(uu, ww, Es, Sl, ng, ngf, a0, a1, a2, flags);
-                    if (PUSH) {
-                        U[q] = uu;
-                        W[q] = ww;
-                    }
+        if (nb & 1)                                  // au holds the last block
+            run_block<T, V, VEC, UNROLL, PUSH>(U, W, last, lane, au, aw, Et, Sl, ng, ngf, hi, a1, a2, flags);
+        // Ragged end of the tile (only the run's last tile): same per-lane
+        // order as a full block, one particle at a time.
+        for (int64_t base = p0 + nb * PER; base < p1; base += PER) {
+            for (int k = 0; k < UNROLL; ++k) {
+                const int64_t i = base + (int64_t)(k * 64 + lane) * VEC;
+                for (int e = 0; e < VEC; ++e) {
+                    const int64_t q = i + e;
+                    if (q < p1) run_one<T, PUSH>(U, W, q, Et, Sl, ng, ngf, hi, a1, a2, flags);
                 }
             }
         }
-        a0 = wave_sum(a0);
         a1 = wave_sum(a1);
         a2 = wave_sum(a2);
         if (lane == 0) {
-            double *pp = part + (size_t)kPartCols * (size_t)t;
-            pp[0] = a0;
-            pp[1] = a1;
-            pp[2] = a2;
+            f64x2 pt;
+            pt.x = a1;
+            pt.y = a2;
+            *reinterpret_cast<f64x2 *>(part + kPartCols * (size_t)t) = pt;
         }
     }
     if (flags) atomicOr(&R->flags, flags);
     __syncthreads();
-    // Merge the private grid into the run's grid.  Start at a block-dependent
-    // rotation so that concurrent flushes hit different addresses.
+    // Merge the private grid into the run's grid with 64-bit atomics, folding
+    // the two ghost nodes.  No fence: the solve runs in the next launch, after
+    // the kernel boundary has made every merge visible.  Starting at a
+    // chunk-dependent rotation spreads concurrent merges over addresses.
     unsigned long long *S = R->S;
-    const int rot = (int)(((unsigned)blockIdx.x * 97u) % (unsigned)ng);
+    const int rot = (int)(((unsigned)chunk * 97u) % (unsigned)ng);
     for (int k = threadIdx.x; k < ng; k += BLOCK) {
-        int g = k + rot;
-        if (g >= ng) g -= ng;
-        const unsigned long long v = Sl[g];
-        if (v) {
-            atomicAdd(S + g, v);
-            Sl[g] = 0ull;
+        int c = k + rot;
+        if (c >= ng) c -= ng;
+        unsigned long long v = Sl[c + 1];
+        Sl[c + 1] = 0ull;
+        if (c == 0) {
+            v += Sl[ng + 1];
+            Sl[ng + 1] = 0ull;
         }
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t n = (uint32_t)(te - tb);
-        const uint32_t prev = atomicAdd(&R->counter, n);
-        *s_last = (prev + n == (uint32_t)R->ntiles) ? 1 : 0;
+        if (c == ng - 1) {
+            v += Sl[0];
+            Sl[0] = 0ull;
+        }
+        if (v) atomicAdd(S + c, v);
     }
     __syncthreads();
-    if (*s_last) {
-        __threadfence();
-        solve_run<BLOCK>(R, reinterpret_cast<double *>(Sl), red, redi, !PUSH);
-    }
 }
 
-template <typename T, int BLOCK, bool PUSH>
-__global__ __launch_bounds__(BLOCK, 6) void step_kernel(RunDev *runs, const WorkItem *items,
-                                                        const int32_t *wg_begin, int ng_lds) {
+template <typename T, int BLOCK, int UNROLL, bool PUSH>
+__global__ __launch_bounds__(BLOCK, (UNROLL >= 4 ? 4 : 6)) void step_kernel(
+    RunDev *runs, const WorkItem *items, const int32_t *wg_begin, int ng_lds) {
     extern __shared__ unsigned long long lds[];
-    __shared__ double red[BLOCK / 64];
-    __shared__ long long redi[BLOCK / 64];
-    __shared__ int s_last;
     unsigned long long *Sl = lds;
-    T *Es = reinterpret_cast<T *>(lds + ng_lds);
-    for (int g = threadIdx.x; g < ng_lds; g += BLOCK) Sl[g] = 0ull;
+    T *Et = reinterpret_cast<T *>(lds + ng_lds + 2);
+    for (int g = threadIdx.x; g < ng_lds + 2; g += BLOCK) Sl[g] = 0ull;
     int ib = 0, ie = 1;
     if (items) {
         ib = wg_begin[blockIdx.x];
@@ -382,54 +469,84 @@ __global__ __launch_bounds__(BLOCK, 6) void step_kernel(RunDev *runs, const Work
     }
     int prev_run = -1;
     for (int it = ib; it < ie; ++it) {
-        int r, tb, te;
+        int r, tb, te, chunk;
         if (items) {
             const WorkItem wi = items[it];
             r = wi.run;
             tb = wi.tile_begin;
             te = wi.tile_end;
+            chunk = wi.chunk;
         } else {
             r = 0;
             const int64_t nt = runs[0].ntiles;
             tb = (int)(nt * blockIdx.x / gridDim.x);
             te = (int)(nt * (blockIdx.x + 1) / gridDim.x);
+            chunk = blockIdx.x;
         }
         RunDev *R = runs + r;
         if (te <= tb || R->step >= R->step_target || R->ng > ng_lds) continue;
-        process_chunk<T, BLOCK, PUSH>(R, tb, te, r != prev_run, Sl, Es, red, redi, &s_last);
+        process_chunk<T, BLOCK, UNROLL, PUSH>(R, tb, te, chunk, r != prev_run, Sl, Et);
         prev_run = r;
     }
 }
 
-template <typename T, int BLOCK, bool PUSH>
+// Second launch of a step: workgroup b solves run runs[b] for E^{n+1} and
+// records the diagnostics; runs that are idle or finished return at once.
+__global__ __launch_bounds__(kSolveThreads) void solve_kernel(RunDev *runs, int prologue) {
+    __shared__ double D[kMaxNg];
+    __shared__ double red[kSolveThreads / 64];
+    __shared__ long long redi[kSolveThreads / 64];
+    RunDev *R = runs + blockIdx.x;
+    if (R->step >= R->step_target) return;
+    solve_run(R, D, red, redi, prologue != 0);
+}
+
+template <typename T, int BLOCK, int UNROLL, bool PUSH>
 const void *kernel_ptr() {
-    return (const void *)step_kernel<T, BLOCK, PUSH>;
+    return (const void *)step_kernel<T, BLOCK, UNROLL, PUSH>;
+}
+
+template <typename T, int BLOCK, bool PUSH>
+const void *kernel_unroll(int unroll) {
+    if constexpr (!PUSH) {
+        (void)unroll;
+        return kernel_ptr<T, BLOCK, 1, PUSH>();
+    } else {
+        switch (unroll) {
+            case 1: return kernel_ptr<T, BLOCK, 1, PUSH>();
+            case 2: return kernel_ptr<T, BLOCK, 2, PUSH>();
+            case 4: return kernel_ptr<T, BLOCK, 4, PUSH>();
+            default: return nullptr;
+        }
+    }
 }
 
 template <typename T, bool PUSH>
-const void *kernel_for(int block) {
+const void *kernel_for(int block, int unroll) {
     switch (block) {
-        case 256: return kernel_ptr<T, 256, PUSH>();
-        case 512: return kernel_ptr<T, 512, PUSH>();
-        case 1024: return kernel_ptr<T, 1024, PUSH>();
+        case 256: return kernel_unroll<T, 256, PUSH>(unroll);
+        case 512: return kernel_unroll<T, 512, PUSH>(unroll);
+        case 1024: return kernel_unroll<T, 1024, PUSH>(unroll);
         default: return nullptr;
     }
 }
 
-const void *kernel_select(int block, int precision, bool push) {
-    if (precision == 0) return push ? kernel_for<float, true>(block) : kernel_for<float, false>(block);
-    return push ? kernel_for<double, true>(block) : kernel_for<double, false>(block);
+const void *kernel_select(const LaunchShape &ls, int precision, bool push) {
+    if (precision == 0)
+        return push ? kernel_for<float, true>(ls.block, ls.unroll) : kernel_for<float, false>(ls.block, 1);
+    return push ? kernel_for<double, true>(ls.block, ls.unroll) : kernel_for<double, false>(ls.block, 1);
 }
 
 }  // namespace
 
 size_t step_lds_bytes(int precision, int ng_lds) {
-    return (size_t)ng_lds * (sizeof(unsigned long long) + (precision ? sizeof(double) : sizeof(float)));
+    return (size_t)(ng_lds + 2) *
+           (sizeof(unsigned long long) + (precision ? sizeof(double) : sizeof(float)));
 }
 
-hipError_t step_prepare(int block, int precision) {
+hipError_t step_prepare(const LaunchShape &ls, int precision) {
     for (int push = 0; push < 2; ++push) {
-        const void *fn = kernel_select(block, precision, push != 0);
+        const void *fn = kernel_select(ls, precision, push != 0);
         if (!fn) return hipErrorInvalidValue;
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)step_lds_bytes(precision, kMaxNg));
@@ -439,20 +556,25 @@ hipError_t step_prepare(int block, int precision) {
 }
 
 hipError_t launch_step(RunDev *runs, const WorkItem *items, const int32_t *wg_begin, int grid,
-                       int block, int ng_lds, int precision, int prologue, hipStream_t stream) {
-    if (grid <= 0 || ng_lds <= 0 || ng_lds > kMaxNg) return hipErrorInvalidValue;
-    const void *fn = kernel_select(block, precision, prologue == 0);
+                       const LaunchShape &ls, int ng_lds, int precision, int prologue, int nsolve,
+                       hipStream_t stream) {
+    if (grid <= 0 || nsolve <= 0 || ng_lds <= 0 || ng_lds > kMaxNg) return hipErrorInvalidValue;
+    const void *fn = kernel_select(ls, precision, prologue == 0);
     if (!fn) return hipErrorInvalidValue;
     void *args[] = {(void *)&runs, (void *)&items, (void *)&wg_begin, (void *)&ng_lds};
-    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, step_lds_bytes(precision, ng_lds),
+    hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(ls.block), args,
+                                   step_lds_bytes(precision, ng_lds), stream);
+    if (e != hipSuccess) return e;
+    void *sargs[] = {(void *)&runs, (void *)&prologue};
+    return hipLaunchKernel((const void *)solve_kernel, dim3(nsolve), dim3(kSolveThreads), sargs, 0,
                            stream);
 }
 
-int step_occupancy(int block, int ng_lds, int precision) {
+int step_occupancy(const LaunchShape &ls, int ng_lds, int precision) {
     int n = 0;
-    const void *fn = kernel_select(block, precision, true);
+    const void *fn = kernel_select(ls, precision, true);
     if (!fn) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, ls.block,
                                                      step_lds_bytes(precision, ng_lds)) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;

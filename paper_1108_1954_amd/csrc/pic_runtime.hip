@@ -16,7 +16,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/pic.h"
+#include "pic.h"
 #include "pic_internal.h"
 
 using namespace pic1d;
@@ -51,7 +51,7 @@ namespace {
 
 struct DeviceInfo {
     int cus = 256;
-    int block = 512;
+    LaunchShape shape;     // default launch shape (overridable for tuning)
 };
 
 DeviceInfo device_info() {
@@ -64,7 +64,11 @@ DeviceInfo device_info() {
     }
     if (const char *b = getenv("PIC1D_BLOCK")) {
         int v = atoi(b);
-        if (v == 256 || v == 512 || v == 1024) d.block = v;
+        if (v == 256 || v == 512 || v == 1024) d.shape.block = v;
+    }
+    if (const char *u = getenv("PIC1D_UNROLL")) {
+        int v = atoi(u);
+        if (v == 1 || v == 2 || v == 4) d.shape.unroll = v;
     }
     return d;
 }
@@ -145,7 +149,7 @@ struct pic_run {
     bool owns_dev = false;
     bool error = false;
     bool batch_member = false;
-    int block = 512;
+    LaunchShape shape;
     int grid = 1;
     double Q = 0, m = 0, dx = 0;
     // graph replay cache
@@ -191,7 +195,7 @@ void fill_constants(pic_run *r) {
     h.tile = r->lay.tile;
     h.ntiles = r->lay.ntiles;
     h.precision = p.precision;
-    h.counter = 0;
+    h.pad0_ = 0;
     h.flags = 0;
     h.dx = r->dx;
     h.qfac = r->Q / (r->dx * 4294967296.0);
@@ -218,32 +222,33 @@ void carve(pic_run *r) {
     h.sort_hist = nullptr;
 }
 
-// Convert host FP64 particles to engine units and upload them.
+// Convert host FP64 particles to engine units and upload them: the stored
+// position is s = x/dx + 1/2 in [1/2, ng + 1/2) (rounded once to the state
+// precision; a value that rounds up to ng + 1/2 is the same point as x = 0)
+// and the velocity w = v dt/dx.
 pic_status upload_particles(pic_run *r, const double *x0, const double *v) {
     const pic_params &p = r->p;
-    const double inv_dx = 1.0 / r->dx;
     const double wscale = p.dt / r->dx;
     const size_t n = (size_t)p.np;
     if (p.precision == PIC_FP32) {
         std::vector<float> u(n), w(n);
-        const float ngf = (float)p.ng;
+        const float hi = (float)p.ng + 0.5f;
         for (size_t i = 0; i < n; ++i) {
-            float ui = (float)(x0[i] / r->dx);
-            if (!(ui < ngf)) ui = 0.0f;   // x just below L can round to ng: same point as 0
-            u[i] = ui;
+            float si = (float)(x0[i] / r->dx + 0.5);
+            if (!(si < hi)) si = 0.5f;
+            u[i] = si;
             w[i] = (float)(v[i] * wscale);
         }
-        (void)inv_dx;
         HIP_TRY(hipMemcpyAsync(r->host.u, u.data(), n * 4, hipMemcpyHostToDevice, r->stream));
         HIP_TRY(hipMemcpyAsync(r->host.w, w.data(), n * 4, hipMemcpyHostToDevice, r->stream));
         HIP_TRY(hipStreamSynchronize(r->stream));
     } else {
         std::vector<double> u(n), w(n);
-        const double ngd = (double)p.ng;
+        const double hi = (double)p.ng + 0.5;
         for (size_t i = 0; i < n; ++i) {
-            double ui = x0[i] / r->dx;
-            if (!(ui < ngd)) ui = 0.0;
-            u[i] = ui;
+            double si = x0[i] / r->dx + 0.5;
+            if (!(si < hi)) si = 0.5;
+            u[i] = si;
             w[i] = v[i] * wscale;
         }
         HIP_TRY(hipMemcpyAsync(r->host.u, u.data(), n * 8, hipMemcpyHostToDevice, r->stream));
@@ -260,16 +265,16 @@ pic_status init_device_state(pic_run *r) {
     HIP_TRY(hipMemsetAsync(r->host.S_last, 0, (size_t)r->p.ng * 8, r->stream));
     HIP_TRY(hipMemsetAsync(r->host.tile_part, 0, (size_t)r->lay.ntiles * kPartCols * 8, r->stream));
     HIP_TRY(hipMemcpyAsync(r->dev, &r->host, sizeof(RunDev), hipMemcpyHostToDevice, r->stream));
-    HIP_TRY(step_prepare(r->block, r->p.precision));
-    HIP_TRY(launch_step(r->dev, nullptr, nullptr, r->grid, r->block, r->p.ng, r->p.precision, 1,
-                        r->stream));
+    HIP_TRY(step_prepare(r->shape, r->p.precision));
+    HIP_TRY(launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng, r->p.precision, 1,
+                        1, r->stream));
     HIP_TRY(hipStreamSynchronize(r->stream));
     return PIC_OK;
 }
 
 int single_run_grid(const pic_run *r, const DeviceInfo &d) {
-    const int occ = step_occupancy(d.block, r->p.ng, r->p.precision);
-    const int waves = d.block / 64;
+    const int occ = step_occupancy(r->shape, r->p.ng, r->p.precision);
+    const int waves = r->shape.block / 64;
     const int want = (r->lay.ntiles + waves - 1) / waves;
     return std::max(1, std::min(want, d.cus * occ));
 }
@@ -277,6 +282,33 @@ int single_run_grid(const pic_run *r, const DeviceInfo &d) {
 pic_status check_run(pic_run *r) {
     if (!r) return fail(PIC_EINVAL, "run is NULL");
     if (r->error) return fail(PIC_ESTATE, "run is in an error state after an earlier device error");
+    return PIC_OK;
+}
+
+// Capture `count` launches made by `launch(stream)` into an executable graph.
+// Capture runs on a private non-blocking stream (the caller's stream may be
+// the legacy default stream, which cannot be captured); the graph is later
+// launched on the caller's stream.
+template <typename F>
+pic_status capture_graph(F launch, int count, hipGraphExec_t *exec) {
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t be = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    hipError_t le = hipSuccess;
+    if (be == hipSuccess) {
+        for (int k = 0; k < count && le == hipSuccess; ++k) le = launch(cs);
+    }
+    hipError_t ce = be == hipSuccess ? hipStreamEndCapture(cs, &g) : be;
+    (void)hipStreamDestroy(cs);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(PIC_EDEVICE, "graph capture failed: %s",
+                    hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    hipError_t ie = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(PIC_EDEVICE, "graph instantiate: %s", hipGetErrorString(ie));
     return PIC_OK;
 }
 
@@ -325,7 +357,7 @@ extern "C" pic_status pic_create(const pic_params *params, const double *x0, con
     }
     r->dev = (RunDev *)(r->base + r->lay.total);
     DeviceInfo d = device_info();
-    r->block = d.block;
+    r->shape = d.shape;
     fill_constants(r);
     carve(r);
     r->grid = single_run_grid(r, d);
@@ -348,8 +380,8 @@ extern "C" pic_status pic_step(pic_run *r, int64_t nsteps) {
     if (r->batch_member) return fail(PIC_ESTATE, "batch members are stepped with pic_batch_step");
     if (nsteps < 0) return fail(PIC_EINVAL, "nsteps must be >= 0");
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(r->dev, nullptr, nullptr, r->grid, r->block, r->p.ng,
-                                   r->p.precision, 0, r->stream);
+        hipError_t e = launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng,
+                                   r->p.precision, 0, 1, r->stream);
         if (e != hipSuccess) {
             r->error = true;
             return fail(PIC_EDEVICE, "step launch failed: %s", hipGetErrorString(e));
@@ -369,21 +401,14 @@ extern "C" pic_status pic_step_graph(pic_run *r, int64_t nsteps, int32_t graph_s
         r->graph = nullptr;
     }
     if (!r->graph && nsteps >= graph_steps) {
-        hipGraph_t g = nullptr;
-        HIP_TRY(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t le = hipSuccess;
-        for (int k = 0; k < graph_steps && le == hipSuccess; ++k)
-            le = launch_step(r->dev, nullptr, nullptr, r->grid, r->block, r->p.ng, r->p.precision, 0,
-                             r->stream);
-        hipError_t ce = hipStreamEndCapture(r->stream, &g);
-        if (le != hipSuccess || ce != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return fail(PIC_EDEVICE, "graph capture failed: %s",
-                        hipGetErrorString(le != hipSuccess ? le : ce));
-        }
-        hipError_t ie = hipGraphInstantiate(&r->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ie != hipSuccess) return fail(PIC_EDEVICE, "graph instantiate: %s", hipGetErrorString(ie));
+        const pic_run *rc = r;
+        pic_status gs = capture_graph(
+            [rc](hipStream_t s) {
+                return launch_step(rc->dev, nullptr, nullptr, rc->grid, rc->shape, rc->p.ng,
+                                   rc->p.precision, 0, 1, s);
+            },
+            graph_steps, &r->graph);
+        if (gs != PIC_OK) return gs;
         r->graph_steps = graph_steps;
     }
     int64_t left = nsteps;
@@ -430,8 +455,19 @@ extern "C" pic_status pic_read_raw(pic_run *r, void *u, void *w, int64_t cap) {
     if (cap < r->p.np) return fail(PIC_EINVAL, "cap %lld < np %lld", (long long)cap, (long long)r->p.np);
     st = sync_run(r);
     if (st != PIC_OK) return st;
-    const size_t bytes = (size_t)r->p.np * r->lay.esize;
-    if (u) HIP_TRY(hipMemcpy(u, r->host.u, bytes, hipMemcpyDeviceToHost));
+    const size_t n = (size_t)r->p.np;
+    const size_t bytes = n * r->lay.esize;
+    if (u) {
+        HIP_TRY(hipMemcpy(u, r->host.u, bytes, hipMemcpyDeviceToHost));
+        // stored s = u + 1/2 with s >= 1/2: s - 1/2 is exact in either precision
+        if (r->p.precision == PIC_FP32) {
+            float *f = (float *)u;
+            for (size_t i = 0; i < n; ++i) f[i] -= 0.5f;
+        } else {
+            double *d = (double *)u;
+            for (size_t i = 0; i < n; ++i) d[i] -= 0.5;
+        }
+    }
     if (w) HIP_TRY(hipMemcpy(w, r->host.w, bytes, hipMemcpyDeviceToHost));
     return PIC_OK;
 }
@@ -582,7 +618,8 @@ struct pic_batch {
     int32_t *wg_host = nullptr;
     hipEvent_t staged = nullptr;      // staging buffers free again
     int item_cap = 0;
-    int grid = 0, block = 512;
+    int grid = 0;
+    LaunchShape shape;
     std::vector<int> free_slots;
     std::map<int64_t, Member> members;
     int64_t next_id = 1;
@@ -607,7 +644,7 @@ pic_status batch_check(pic_batch *b) {
 // chunks go, largest first, to the least-loaded workgroup.
 pic_status rebuild_schedule(pic_batch *b) {
     struct Chunk {
-        int slot, tb, te;
+        int slot, tb, te, index, count;
         int64_t work;
     };
     std::vector<Chunk> chunks;
@@ -623,10 +660,11 @@ pic_status rebuild_schedule(pic_batch *b) {
         if (m.launch_done <= b->launches) continue;
         const int tile = m.run->lay.tile, nt = m.run->lay.ntiles;
         const int per = (int)std::max<int64_t>(1, (target + tile - 1) / tile);
-        for (int t0 = 0; t0 < nt; t0 += per) {
+        const int count = (nt + per - 1) / per;
+        for (int c = 0, t0 = 0; t0 < nt; ++c, t0 += per) {
             int t1 = std::min(nt, t0 + per);
             int64_t w = std::min<int64_t>((int64_t)t1 * tile, m.run->p.np) - (int64_t)t0 * tile;
-            chunks.push_back({m.slot, t0, t1, w + 4 * m.run->p.ng});
+            chunks.push_back({m.slot, t0, t1, c, count, w + 4 * m.run->p.ng});
         }
     }
     std::sort(chunks.begin(), chunks.end(), [](const Chunk &a, const Chunk &c) {
@@ -639,7 +677,7 @@ pic_status rebuild_schedule(pic_batch *b) {
     for (const Chunk &c : chunks) {
         size_t k = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
         load[k] += c.work;
-        per_wg[k].push_back({c.slot, c.tb, c.te, 0});
+        per_wg[k].push_back({c.slot, c.tb, c.te, c.index, c.count, 0});
     }
     if ((int)chunks.size() > b->item_cap)
         return fail(PIC_ENOMEM, "work list of %zu chunks exceeds capacity %d", chunks.size(), b->item_cap);
@@ -672,8 +710,8 @@ int64_t next_completion(const pic_batch *b) {
 }
 
 pic_status batch_launch_one(pic_batch *b) {
-    hipError_t e = launch_step(b->table, b->items_dev, b->wg_dev, b->grid, b->block, b->cfg.ng_max,
-                               PIC_FP32, 0, b->stream);
+    hipError_t e = launch_step(b->table, b->items_dev, b->wg_dev, b->grid, b->shape, b->cfg.ng_max,
+                               PIC_FP32, 0, b->cfg.max_runs, b->stream);
     if (e != hipSuccess) {
         b->error = true;
         return fail(PIC_EDEVICE, "batch step launch failed: %s", hipGetErrorString(e));
@@ -683,22 +721,13 @@ pic_status batch_launch_one(pic_batch *b) {
 
 pic_status ensure_graph(pic_batch *b) {
     if (b->graph || b->cfg.graph_steps <= 1) return PIC_OK;
-    hipGraph_t g = nullptr;
-    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = hipSuccess;
-    for (int k = 0; k < b->cfg.graph_steps && le == hipSuccess; ++k)
-        le = launch_step(b->table, b->items_dev, b->wg_dev, b->grid, b->block, b->cfg.ng_max, PIC_FP32,
-                         0, b->stream);
-    hipError_t ce = hipStreamEndCapture(b->stream, &g);
-    if (le != hipSuccess || ce != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return fail(PIC_EDEVICE, "batch graph capture failed: %s",
-                    hipGetErrorString(le != hipSuccess ? le : ce));
-    }
-    hipError_t ie = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ie != hipSuccess) return fail(PIC_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(ie));
-    return PIC_OK;
+    const pic_batch *bc = b;
+    return capture_graph(
+        [bc](hipStream_t s) {
+            return launch_step(bc->table, bc->items_dev, bc->wg_dev, bc->grid, bc->shape,
+                               bc->cfg.ng_max, PIC_FP32, 0, bc->cfg.max_runs, s);
+        },
+        b->cfg.graph_steps, &b->graph);
 }
 
 pic_status add_mark(pic_batch *b) {
@@ -738,13 +767,13 @@ extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream
     b->cfg = *cfg;
     b->stream = (hipStream_t)stream;
     DeviceInfo d = device_info();
-    b->block = d.block;
-    hipError_t e = step_prepare(b->block, PIC_FP32);
+    b->shape = d.shape;
+    hipError_t e = step_prepare(b->shape, PIC_FP32);
     if (e != hipSuccess) {
         delete b;
         return fail(PIC_EDEVICE, "kernel setup: %s", hipGetErrorString(e));
     }
-    const int occ = step_occupancy(b->block, cfg->ng_max, PIC_FP32);
+    const int occ = step_occupancy(b->shape, cfg->ng_max, PIC_FP32);
     b->grid = cfg->grid_blocks > 0 ? cfg->grid_blocks : d.cus * occ;
     b->item_cap = 4 * b->grid + 4 * cfg->max_runs;
     bool ok = true;
@@ -766,6 +795,20 @@ extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream
     }
     b->arena.reset(cfg->hbm_budget);
     for (int s = cfg->max_runs - 1; s >= 0; --s) b->free_slots.push_back(s);
+    {
+        // Every slot starts idle (step == step_target): the solve launch
+        // covers all slots and returns at once for idle ones.
+        std::vector<RunDev> idle((size_t)cfg->max_runs);
+        for (RunDev &d : idle) {
+            d = RunDev{};
+            d.ng = 2;
+        }
+        if (hipMemcpy(b->table, idle.data(), sizeof(RunDev) * idle.size(), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            pic_batch_destroy(b);
+            return fail(PIC_EDEVICE, "run table initialisation failed");
+        }
+    }
     if (hipEventRecord(b->staged, b->stream) != hipSuccess) {
         pic_batch_destroy(b);
         return fail(PIC_EDEVICE, "event record failed");
@@ -805,7 +848,7 @@ extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, co
     r->stream = b->stream;
     r->base = b->arena_base + off;
     r->batch_member = true;
-    r->block = b->block;
+    r->shape = b->shape;
     const int slot = b->free_slots.back();
     b->free_slots.pop_back();
     r->dev = b->table + slot;

@@ -55,13 +55,19 @@ def solve_tolerance(p, S):
 
 
 def push_tolerance(u_new, w_new, Ehat_max, ng, eps):
-    """One step in precision eps against the exact (FP64) step from the same
-    state and the same field:  the gather weight f has at most one rounding,
-    the stored table Ehat one, E_{j+1} - E_j and the FMA one each, so
-    |dEp| <= 6 eps max|Ehat|; the kick adds eps |w_new|; the drift eps |u_new|
-    and the wrap eps ng.  A factor 2 covers the FP64 side and conversions."""
-    dw = 2 * eps * (np.abs(w_new) + 6 * Ehat_max)
-    du = dw + 2 * eps * (np.abs(u_new) + ng)
+    """One GPU step in precision eps against the oracle's FP64 step from the
+    same state and field.  GPU side: the gather weight f has at most one
+    rounding, the stored table Ehat one, E_{j+1} - E_j and the FMA one each,
+    so |dEp| <= 6 eps max|Ehat|; the kick adds eps |w_new|; the drift
+    eps |u_new| and the wrap eps ng (factor 2 margin).  Oracle side: its FP64
+    gather, kick, drift and wrap plus the unit conversions u <-> x, w <-> v
+    add up to 8 roundings of the same magnitudes in FP64; in particular the
+    oracle's position x/dx = (u dx)/dx is off by up to 2 ulp(ng), which moves
+    its gather weight by that much and Ep by that times the field step
+    |Ehat_{j+1} - Ehat_j| <= 2 max|Ehat|."""
+    conv = 8 * EPS64 * ng * 2 * Ehat_max
+    dw = (2 * eps + 8 * EPS64) * (np.abs(w_new) + 6 * Ehat_max) + conv
+    du = dw + (2 * eps + 8 * EPS64) * (np.abs(u_new) + ng)
     return du, dw
 
 
