@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the 1D electrostatic PIC engine on one MI355X.
+
+Metric: particle-steps/s on one GPU, batched vs plain (one particle-step = one
+particle through gather, kick, drift, wrap and deposit, with its run's field
+solve amortised in).  Default workload: the batched ensemble of 256
+independent runs (Np log-uniform in [1e4, 4e6], Ng in {64, ..., 2048},
+L = 0.032 Ng, two warm beams, dt = 0.1), stepped by one persistent particle
+launch plus one solve launch per step from a captured HIP graph.  The same
+runs are also stepped one after another on the plain per-run path (ordinary
+launches sized to each run), and a single large warm two-stream run
+(Np = 2^26, Ng = 4096) is timed for reference.  `--serving` adds the
+continuous-batching serving measurement (p50/p99 run latency).
+
+Prints ONE JSON line.  Inputs are seeded and synthetic; particle state is
+resident in HBM before the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0          # MI355X HBM3E peak
+BYTES_PER_PSTEP = 16            # FP32 state: read x, v; write x, v
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nruns", type=int, default=256)
+    ap.add_argument("--np-scale", type=float, default=1.0, help="shrink every ensemble run (smoke use)")
+    ap.add_argument("--graph-steps", type=int, default=20)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", action="store_true", help="also run the serving load")
+    ap.add_argument("--serving-runs", type=int, default=300)
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("pic_kernels.hip", "pic_internal.h"):
+        with open(os.path.join(ROOT, "paper_1108_1954_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per particle-pass launch from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload)
+    if not e or e.get("kernel_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def generate(specs):
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(lambda s: s.particles(), specs))
+
+
+def cpu_baseline(spec, parts, budget_s=15.0):
+    """The FP64 oracle as it stands, on one host core, on a bounded sample of
+    the workload: one ensemble run, stepped long enough for ~budget_s."""
+    from oracle import oracle as O
+    x, v = parts
+    p = O.params(spec.L, spec.ng, spec.np_, dt=spec.dt)
+    t = time.perf_counter()
+    O.run(p, x, v, 2, mode=O.DEPOSIT_FIXED)
+    per_step = (time.perf_counter() - t) / 2
+    n = max(2, int(budget_s / max(per_step, 1e-6)))
+    t = time.perf_counter()
+    O.run(p, x, v, n, mode=O.DEPOSIT_FIXED)
+    dt = time.perf_counter() - t
+    return {"value": spec.np_ * n / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle (fixed-point deposit), one ensemble run np={spec.np_} ng={spec.ng}, "
+                      f"{n} steps, {dt:.1f} s, single thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the engine shards across GPUs "
+              "only by design (see the design notes), no multi-GPU path is measured.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1108_1954_amd import inputs as I
+    from paper_1108_1954_amd import pic as P
+    P.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.cuda.get_device_properties(0)
+    stream = P.current_stream()
+    K, W = args.steps, args.warmup
+
+    # ------------------------------------------------------------ ensemble
+    t0 = time.perf_counter()
+    specs = I.ensemble(nruns=args.nruns, seed=3, nsteps=500, np_scale=args.np_scale)
+    parts = generate(specs)
+    total_np = sum(s.np_ for s in specs)
+    log(f"ensemble: {len(specs)} runs, {total_np} particles, generated in {time.perf_counter() - t0:.1f} s")
+    prof_steps = 5
+    run_steps = W + K + prof_steps + 1
+    params = [P.make_params(s.L, s.ng, s.np_, s.dt, history_cap=run_steps) for s in specs]
+    budget = int(sum(P.pic_footprint(p) for p in params) * 1.05) + (64 << 20)
+    ng_max = max(s.ng for s in specs)
+    b = P.pic_batch_create(budget, ng_max, max_runs=len(specs), graph_steps=args.graph_steps, stream=stream)
+    t0 = time.perf_counter()
+    for p, (x, v) in zip(params, parts):
+        P.pic_batch_admit(b, p, x, v, run_steps)
+    torch.cuda.synchronize()
+    log(f"admitted in {time.perf_counter() - t0:.1f} s")
+    P.pic_batch_step(b, W)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    P.pic_batch_step(b, K)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev0.elapsed_time(ev1) / K
+    batched_rate = total_np * K / wall
+    ms_particle, ms_solve = P.pic_batch_step_profiled(b, prof_steps)
+    torch.cuda.synchronize()
+    d0, _, _ = P.pic_diagnostics(P.pic_batch_run(b, 1))
+    assert d0["charge_fixed_sum"] == specs[0].np_ << 32
+    P.pic_batch_destroy(b)
+    log(f"batched: {ms_step:.3f} ms/step (events), {batched_rate:.4g} particle-steps/s (wall), "
+        f"particle pass {ms_particle:.3f} ms, solve {ms_solve:.3f} ms")
+
+    # ---------------------------------------------------- plain per-run path
+    plain = None
+    if not args.no_plain:
+        runs = [P.Run(p, x, v) for p, (x, v) in zip(params, parts)]
+        for r in runs:
+            r.step(W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in runs:                        # runs one after another, plain launches
+            r.step(K)
+        torch.cuda.synchronize()
+        wall_p = time.perf_counter() - t0
+        plain = {"value": total_np * K / wall_p, "ms_per_step": 1e3 * wall_p / K,
+                 "path": "same kernels, one plain launch pair per run per step, runs in sequence"}
+        for r in runs:
+            r.close()
+        log(f"plain: {plain['ms_per_step']:.3f} ms/step, {plain['value']:.4g} particle-steps/s")
+
+    # ------------------------------------------------- single large run (c2)
+    single = None
+    if not args.no_single:
+        s2 = I.warm_two_stream_large(np_=1 << 26, ng=4096, nsteps=1000)
+        x, v = s2.particles()
+        p2 = P.make_params(s2.L, s2.ng, s2.np_, s2.dt)
+        r2 = P.Run(p2, x, v)
+        del x, v
+        r2.step(W + args.graph_steps, graph_steps=args.graph_steps)      # warm, incl. graph capture
+        torch.cuda.synchronize()
+        ev0.record()
+        r2.step(K, graph_steps=args.graph_steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms2 = ev0.elapsed_time(ev1) / K
+        mp2, msv2 = P.pic_step_profiled(r2.handle, prof_steps)
+        r2.close()
+        single = {"workload": "warm two-stream, np=2^26, ng=4096, L=131.39, dt=0.1",
+                  "value": s2.np_ / (ms2 * 1e-3), "ms_per_step": ms2,
+                  "particle_pass_ms": mp2, "solve_ms": msv2,
+                  "particle_pass_GBps": BYTES_PER_PSTEP * s2.np_ / (mp2 * 1e6)}
+        log(f"single run: {ms2:.3f} ms/step, particle pass {mp2:.3f} ms, solve {msv2:.3f} ms")
+
+    # ------------------------------------------------------------- serving
+    serving = None
+    if args.serving:
+        from paper_1108_1954_amd import serve
+        serving = serve.serve_load(nruns=args.serving_runs, np_scale=args.np_scale, stream=stream)
+        log(f"serving: {serving}")
+
+    # --------------------------------------------------------- CPU baseline
+    cpu = None
+    if not args.no_cpu_baseline:
+        k = int(np.argsort([s.np_ for s in specs])[len(specs) // 2])     # median-size run
+        cpu = cpu_baseline(specs[k], parts[k])
+        log(f"cpu baseline: {cpu}")
+
+    achieved = BYTES_PER_PSTEP * total_np / (ms_particle * 1e6)   # GB/s of the particle pass
+    out = {
+        "metric": "particle-steps/s on 1 GPU, batched vs plain; p50/p99 run latency under load",
+        "value": batched_rate,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "numerics": "f32 particle state and push, int64 fixed-point deposit, f64 solve and diagnostics",
+        "data": "synthetic (seeded SplitMix64 inputs)",
+        "config": {"workload": f"batched ensemble: {len(specs)} runs, Np log-uniform [1e4,4e6]"
+                               f"{'' if args.np_scale == 1.0 else f' x{args.np_scale}'}, Ng 64..2048, "
+                               "L=0.032 Ng, dt=0.1, one graph-captured persistent launch pair per step",
+                   "total_particles": total_np, "runs": len(specs), "ng_max": ng_max,
+                   "graph_steps": args.graph_steps, "device": dev.name, "cus": dev.multi_processor_count},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBPS, "traffic": measured_traffic("ensemble"),
+                     "kernel": "step_kernel (particle pass)", "kernel_ms": ms_particle,
+                     "bytes_per_launch": BYTES_PER_PSTEP * total_np, "solve_ms": ms_solve},
+        "plain": plain,
+        "batched_vs_plain": (batched_rate / plain["value"]) if plain else None,
+        "single_run": single,
+        "serving": serving,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

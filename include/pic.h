@@ -131,6 +131,12 @@ pic_status pic_step(pic_run *run, int64_t nsteps);
  * `graph_steps` launches (captured on first use, reused afterwards). */
 pic_status pic_step_graph(pic_run *run, int64_t nsteps, int32_t graph_steps);
 
+/* Enqueue `nsteps` >= 1 plain (ungraphed) steps with HIP events around each
+ * of the step's two launches (particle pass, field solve), wait for them,
+ * and report the mean duration of each launch in milliseconds.  For
+ * measurement; the steps are real and advance the run. */
+pic_status pic_step_profiled(pic_run *run, int64_t nsteps, double *ms_particle, double *ms_solve);
+
 /* Synchronise the run's stream and report diagnostics of the current state.
  * rho_out/E_out (FP64, ng_cap >= ng entries) may be NULL. */
 pic_status pic_diagnostics(pic_run *run, pic_diag *diag, double *rho_out, double *E_out,
@@ -187,6 +193,12 @@ pic_status pic_batch_admit(pic_batch *b, const pic_params *params, const double 
 
 /* Advance every unfinished run by up to `nsteps` steps (asynchronous). */
 pic_status pic_batch_step(pic_batch *b, int64_t nsteps);
+
+/* pic_batch_step with HIP events around each launch (no graph), waiting
+ * for completion and reporting the mean particle-pass and solve durations
+ * in milliseconds over the launches issued. */
+pic_status pic_batch_step_profiled(pic_batch *b, int64_t nsteps, double *ms_particle,
+                                   double *ms_solve);
 
 /* Report runs that reached their step count since the last poll
  * (non-blocking: only completed device work is reported). */

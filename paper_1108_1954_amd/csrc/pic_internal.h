@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+#include <string>
+
 namespace pic1d {
 
 constexpr int kMaxNg = 8192;
@@ -74,9 +77,19 @@ struct LaunchShape {
 //   The solve launch has nsolve workgroups; workgroup b solves runs[b]
 //   (idle and finished runs return at once).
 //   prologue != 0: deposit + solve only (creation), no push.
+//   ev (optional): events recorded before the particle pass (e0), between
+//   the two launches (e1) and after the solve (e2).
+struct StepEvents {
+    hipEvent_t e0, e1, e2;
+};
 hipError_t launch_step(RunDev *runs, const WorkItem *items, const int32_t *wg_begin,
                        int grid, const LaunchShape &shape, int ng_lds, int precision, int prologue,
-                       int nsolve, hipStream_t stream);
+                       int nsolve, hipStream_t stream, const StepEvents *ev = nullptr);
+
+// The particle pass alone (used by the autotuner on saved state).
+hipError_t launch_particles(RunDev *runs, const WorkItem *items, const int32_t *wg_begin,
+                            int grid, const LaunchShape &shape, int ng_lds, int precision,
+                            int prologue, hipStream_t stream);
 
 // Allow the step kernels of this shape/precision the LDS they need (called
 // once before the first launch and before any graph capture).
@@ -88,5 +101,13 @@ int step_occupancy(const LaunchShape &shape, int ng_lds, int precision);
 // Dynamic LDS of one workgroup: the int64 grid plus the gather table, each
 // with two ghost nodes.
 size_t step_lds_bytes(int precision, int ng_lds);
+
+// Autotuner (pic_tune.hip).  tune_key names a size class; tune_lookup finds
+// a cached shape; tune_shapes times `launch(shape)` (one particle pass on
+// saved state) for every candidate and caches and returns the fastest.
+std::string tune_key(const char *kind, int precision, int ng, int64_t np);
+bool tune_lookup(const std::string &key, LaunchShape *out);
+hipError_t tune_shapes(const std::string &key, int precision, hipStream_t stream,
+                       const std::function<hipError_t(const LaunchShape &)> &launch, LaunchShape *best);
 
 }  // namespace pic1d

@@ -409,14 +409,23 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
         }
         if (nb & 1)                                  // au holds the last block
             run_block<T, V, VEC, UNROLL, PUSH>(U, W, last, lane, au, aw, Et, Sl, ng, ngf, hi, a1, a2, flags);
-        // Ragged end of the tile (only the run's last tile): same per-lane
-        // order as a full block, one particle at a time.
+        // Ragged end of the tile (only a run's last tile): same per-lane
+        // order as a full block; whole vectors where they fit, then single
+        // particles.
         for (int64_t base = p0 + nb * PER; base < p1; base += PER) {
             for (int k = 0; k < UNROLL; ++k) {
                 const int64_t i = base + (int64_t)(k * 64 + lane) * VEC;
-                for (int e = 0; e < VEC; ++e) {
-                    const int64_t q = i + e;
-                    if (q < p1) run_one<T, PUSH>(U, W, q, Et, Sl, ng, ngf, hi, a1, a2, flags);
+                if (i + VEC <= p1) {
+                    V vu[1], vw[1];
+                    vu[0] = load_stream<V>(U + i);
+                    vw[0] = load_stream<V>(W + i);
+                    run_block<T, V, VEC, 1, PUSH>(U, W, i - (int64_t)lane * VEC, lane, vu, vw, Et, Sl, ng,
+                                                  ngf, hi, a1, a2, flags);
+                } else {
+                    for (int e = 0; e < VEC; ++e) {
+                        const int64_t q = i + e;
+                        if (q < p1) run_one<T, PUSH>(U, W, q, Et, Sl, ng, ngf, hi, a1, a2, flags);
+                    }
                 }
             }
         }
@@ -555,19 +564,31 @@ hipError_t step_prepare(const LaunchShape &ls, int precision) {
     return hipSuccess;
 }
 
-hipError_t launch_step(RunDev *runs, const WorkItem *items, const int32_t *wg_begin, int grid,
-                       const LaunchShape &ls, int ng_lds, int precision, int prologue, int nsolve,
-                       hipStream_t stream) {
-    if (grid <= 0 || nsolve <= 0 || ng_lds <= 0 || ng_lds > kMaxNg) return hipErrorInvalidValue;
+hipError_t launch_particles(RunDev *runs, const WorkItem *items, const int32_t *wg_begin, int grid,
+                            const LaunchShape &ls, int ng_lds, int precision, int prologue,
+                            hipStream_t stream) {
+    if (grid <= 0 || ng_lds <= 0 || ng_lds > kMaxNg) return hipErrorInvalidValue;
     const void *fn = kernel_select(ls, precision, prologue == 0);
     if (!fn) return hipErrorInvalidValue;
     void *args[] = {(void *)&runs, (void *)&items, (void *)&wg_begin, (void *)&ng_lds};
-    hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(ls.block), args,
-                                   step_lds_bytes(precision, ng_lds), stream);
-    if (e != hipSuccess) return e;
-    void *sargs[] = {(void *)&runs, (void *)&prologue};
-    return hipLaunchKernel((const void *)solve_kernel, dim3(nsolve), dim3(kSolveThreads), sargs, 0,
+    return hipLaunchKernel(fn, dim3(grid), dim3(ls.block), args, step_lds_bytes(precision, ng_lds),
                            stream);
+}
+
+hipError_t launch_step(RunDev *runs, const WorkItem *items, const int32_t *wg_begin, int grid,
+                       const LaunchShape &ls, int ng_lds, int precision, int prologue, int nsolve,
+                       hipStream_t stream, const StepEvents *ev) {
+    if (nsolve <= 0) return hipErrorInvalidValue;
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev->e0, stream)) != hipSuccess) return e;
+    e = launch_particles(runs, items, wg_begin, grid, ls, ng_lds, precision, prologue, stream);
+    if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev->e1, stream)) != hipSuccess) return e;
+    void *sargs[] = {(void *)&runs, (void *)&prologue};
+    e = hipLaunchKernel((const void *)solve_kernel, dim3(nsolve), dim3(kSolveThreads), sargs, 0, stream);
+    if (e != hipSuccess) return e;
+    if (ev) return hipEventRecord(ev->e2, stream);
+    return hipSuccess;
 }
 
 int step_occupancy(const LaunchShape &ls, int ng_lds, int precision) {

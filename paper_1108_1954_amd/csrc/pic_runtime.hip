@@ -51,7 +51,9 @@ namespace {
 
 struct DeviceInfo {
     int cus = 256;
-    LaunchShape shape;     // default launch shape (overridable for tuning)
+    LaunchShape shape;     // default launch shape
+    bool forced = false;   // shape set through PIC1D_BLOCK / PIC1D_UNROLL
+    bool autotune = true;  // PIC1D_AUTOTUNE=0 turns the autotuner off
 };
 
 DeviceInfo device_info() {
@@ -62,14 +64,23 @@ DeviceInfo device_info() {
         if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
             d.cus = n;
     }
+    d.shape.block = 1024;
+    d.shape.unroll = 1;
     if (const char *b = getenv("PIC1D_BLOCK")) {
         int v = atoi(b);
-        if (v == 256 || v == 512 || v == 1024) d.shape.block = v;
+        if (v == 256 || v == 512 || v == 1024) {
+            d.shape.block = v;
+            d.forced = true;
+        }
     }
     if (const char *u = getenv("PIC1D_UNROLL")) {
         int v = atoi(u);
-        if (v == 1 || v == 2 || v == 4) d.shape.unroll = v;
+        if (v == 1 || v == 2 || v == 4) {
+            d.shape.unroll = v;
+            d.forced = true;
+        }
     }
+    if (const char *a = getenv("PIC1D_AUTOTUNE")) d.autotune = atoi(a) != 0;
     return d;
 }
 
@@ -93,11 +104,13 @@ pic_status validate(const pic_params *p) {
     return PIC_OK;
 }
 
-// Particles per tile: a pure function of (np, ng) so that every launch shape
-// sees the same tiles (and the same diagnostic summation order).
+// Particles per tile: a pure function of np, so that every launch shape and
+// schedule sees the same tiles (and the same diagnostic summation order).
+// At least 1024 (a full vector block for every unroll), at most 16384, and
+// about np/1024 otherwise so that large runs give every wavefront a tile.
 int default_tile(int64_t np) {
-    int64_t t = 256;
-    while (t < 8192 && t * 8192 < np) t *= 2;
+    int64_t t = 1024;
+    while (t < 16384 && t * 1024 < np) t *= 2;
     return (int)t;
 }
 
@@ -272,11 +285,70 @@ pic_status init_device_state(pic_run *r) {
     return PIC_OK;
 }
 
-int single_run_grid(const pic_run *r, const DeviceInfo &d) {
-    const int occ = step_occupancy(r->shape, r->p.ng, r->p.precision);
-    const int waves = r->shape.block / 64;
-    const int want = (r->lay.ntiles + waves - 1) / waves;
-    return std::max(1, std::min(want, d.cus * occ));
+// Workgroups of a single run's particle pass: enough to give each wavefront
+// a tile, at least 16K particles per workgroup (fewer workgroups merging into
+// the same grid for small runs), at most what is resident at once.
+// Copy a run's particle arrays to/from a scratch buffer (autotuning runs
+// real particle passes on the run's own state and then puts it back).
+pic_status save_particles(const pic_run *r, char *dst, bool restore) {
+    const size_t bytes = (size_t)r->p.np * r->lay.esize;
+    char *u = (char *)r->host.u, *w = (char *)r->host.w;
+    if (restore) {
+        HIP_TRY(hipMemcpyAsync(u, dst, bytes, hipMemcpyDeviceToDevice, r->stream));
+        HIP_TRY(hipMemcpyAsync(w, dst + bytes, bytes, hipMemcpyDeviceToDevice, r->stream));
+        // passes without solves only accumulated into S; clear it and any flag
+        HIP_TRY(hipMemsetAsync(r->host.S, 0, (size_t)r->p.ng * 8, r->stream));
+        HIP_TRY(hipMemsetAsync(&r->dev->flags, 0, sizeof(uint32_t), r->stream));
+    } else {
+        HIP_TRY(hipMemcpyAsync(dst, u, bytes, hipMemcpyDeviceToDevice, r->stream));
+        HIP_TRY(hipMemcpyAsync(dst + bytes, w, bytes, hipMemcpyDeviceToDevice, r->stream));
+    }
+    return PIC_OK;
+}
+
+int single_run_grid(const pic_run *r, const LaunchShape &shape, int cus) {
+    const int occ = step_occupancy(shape, r->p.ng, r->p.precision);
+    const int waves = shape.block / 64;
+    int64_t want = (r->lay.ntiles + waves - 1) / waves;
+    want = std::min<int64_t>(want, (r->p.np + 16383) / 16384);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * occ));
+}
+
+// Launch shape of a run: forced by the environment, else cached or tuned
+// for the run's size class, else the default.
+pic_status choose_shape(pic_run *r, const DeviceInfo &d) {
+    LaunchShape shape = d.shape;
+    if (!d.forced && d.autotune) {
+        const std::string key = tune_key("run", r->p.precision, r->p.ng, r->p.np);
+        if (!tune_lookup(key, &shape)) {
+            char *tmp = nullptr;
+            const size_t bytes = 2 * (size_t)r->p.np * r->lay.esize;
+            if (hipMalloc((void **)&tmp, bytes) != hipSuccess)
+                return fail(PIC_ENOMEM, "autotune scratch of %zu bytes", bytes);
+            pic_status st = save_particles(r, tmp, false);
+            hipError_t te = hipSuccess;
+            if (st == PIC_OK) {
+                const int cus = d.cus;
+                te = tune_shapes(key, r->p.precision, r->stream,
+                                 [r, cus](const LaunchShape &s) {
+                                     return launch_particles(r->dev, nullptr, nullptr,
+                                                             single_run_grid(r, s, cus), s, r->p.ng,
+                                                             r->p.precision, 0, r->stream);
+                                 },
+                                 &shape);
+                st = save_particles(r, tmp, true);
+            }
+            hipError_t se = hipStreamSynchronize(r->stream);
+            (void)hipFree(tmp);
+            if (st != PIC_OK) return st;
+            if (te != hipSuccess) return fail(PIC_EDEVICE, "autotune: %s", hipGetErrorString(te));
+            if (se != hipSuccess) return fail(PIC_EDEVICE, "autotune: %s", hipGetErrorString(se));
+        }
+    }
+    r->shape = shape;
+    HIP_TRY(step_prepare(r->shape, r->p.precision));
+    r->grid = single_run_grid(r, r->shape, d.cus);
+    return PIC_OK;
 }
 
 pic_status check_run(pic_run *r) {
@@ -360,9 +432,10 @@ extern "C" pic_status pic_create(const pic_params *params, const double *x0, con
     r->shape = d.shape;
     fill_constants(r);
     carve(r);
-    r->grid = single_run_grid(r, d);
+    r->grid = single_run_grid(r, r->shape, d.cus);
     st = upload_particles(r, x0, v_mhalf);
     if (st == PIC_OK) st = init_device_state(r);
+    if (st == PIC_OK) st = choose_shape(r, d);
     if (st != PIC_OK) {
         std::string msg = g_err;
         if (r->owns_mem) (void)hipFree(r->base);
@@ -417,6 +490,60 @@ extern "C" pic_status pic_step_graph(pic_run *r, int64_t nsteps, int32_t graph_s
         left -= graph_steps;
     }
     return pic_step(r, left);
+}
+
+namespace {
+
+// Launch `n` steps with events around each launch and average the durations.
+template <typename F>
+pic_status profiled_steps(F launch, hipStream_t stream, int64_t n, double *ms_particle,
+                          double *ms_solve) {
+    std::vector<StepEvents> evs((size_t)n);
+    for (auto &e : evs) {
+        HIP_TRY(hipEventCreate(&e.e0));
+        HIP_TRY(hipEventCreate(&e.e1));
+        HIP_TRY(hipEventCreate(&e.e2));
+    }
+    pic_status st = PIC_OK;
+    for (int64_t i = 0; i < n && st == PIC_OK; ++i) st = launch(&evs[(size_t)i]);
+    hipError_t se = hipStreamSynchronize(stream);
+    double a = 0, b = 0;
+    for (auto &e : evs) {
+        float t1 = 0, t2 = 0;
+        if (st == PIC_OK && se == hipSuccess) {
+            (void)hipEventElapsedTime(&t1, e.e0, e.e1);
+            (void)hipEventElapsedTime(&t2, e.e1, e.e2);
+        }
+        a += t1;
+        b += t2;
+        (void)hipEventDestroy(e.e0);
+        (void)hipEventDestroy(e.e1);
+        (void)hipEventDestroy(e.e2);
+    }
+    if (st != PIC_OK) return st;
+    if (se != hipSuccess) return fail(PIC_EDEVICE, "device error: %s", hipGetErrorString(se));
+    if (ms_particle) *ms_particle = a / (double)n;
+    if (ms_solve) *ms_solve = b / (double)n;
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" pic_status pic_step_profiled(pic_run *r, int64_t nsteps, double *ms_particle,
+                                        double *ms_solve) {
+    pic_status st = check_run(r);
+    if (st != PIC_OK) return st;
+    if (r->batch_member) return fail(PIC_ESTATE, "batch members are stepped with pic_batch_step");
+    if (nsteps < 1) return fail(PIC_EINVAL, "nsteps must be >= 1");
+    st = profiled_steps(
+        [r](const StepEvents *ev) {
+            hipError_t e = launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng,
+                                       r->p.precision, 0, 1, r->stream, ev);
+            return e == hipSuccess ? PIC_OK : fail(PIC_EDEVICE, "step launch: %s", hipGetErrorString(e));
+        },
+        r->stream, nsteps, ms_particle, ms_solve);
+    if (st == PIC_EDEVICE) r->error = true;
+    return st;
 }
 
 extern "C" pic_status pic_diagnostics(pic_run *r, pic_diag *diag, double *rho_out, double *E_out,
@@ -618,8 +745,10 @@ struct pic_batch {
     int32_t *wg_host = nullptr;
     hipEvent_t staged = nullptr;      // staging buffers free again
     int item_cap = 0;
-    int grid = 0;
+    int grid = 0, grid_max = 0, cus = 256;
     LaunchShape shape;
+    bool shape_forced = false, autotune = true;
+    std::string tuned_key;                 // size class the shape was chosen for
     std::vector<int> free_slots;
     std::map<int64_t, Member> members;
     int64_t next_id = 1;
@@ -709,16 +838,6 @@ int64_t next_completion(const pic_batch *b) {
     return best;
 }
 
-pic_status batch_launch_one(pic_batch *b) {
-    hipError_t e = launch_step(b->table, b->items_dev, b->wg_dev, b->grid, b->shape, b->cfg.ng_max,
-                               PIC_FP32, 0, b->cfg.max_runs, b->stream);
-    if (e != hipSuccess) {
-        b->error = true;
-        return fail(PIC_EDEVICE, "batch step launch failed: %s", hipGetErrorString(e));
-    }
-    return PIC_OK;
-}
-
 pic_status ensure_graph(pic_batch *b) {
     if (b->graph || b->cfg.graph_steps <= 1) return PIC_OK;
     const pic_batch *bc = b;
@@ -768,6 +887,9 @@ extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream
     b->stream = (hipStream_t)stream;
     DeviceInfo d = device_info();
     b->shape = d.shape;
+    b->shape_forced = d.forced || cfg->grid_blocks > 0;
+    b->autotune = d.autotune;
+    b->cus = d.cus;
     hipError_t e = step_prepare(b->shape, PIC_FP32);
     if (e != hipSuccess) {
         delete b;
@@ -775,7 +897,8 @@ extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream
     }
     const int occ = step_occupancy(b->shape, cfg->ng_max, PIC_FP32);
     b->grid = cfg->grid_blocks > 0 ? cfg->grid_blocks : d.cus * occ;
-    b->item_cap = 4 * b->grid + 4 * cfg->max_runs;
+    b->grid_max = std::max(b->grid, d.cus * 16);      // room for any tuned shape
+    b->item_cap = 4 * b->grid_max + 4 * cfg->max_runs;
     bool ok = true;
     if (cfg->arena) {
         b->arena_base = (char *)cfg->arena;
@@ -785,9 +908,9 @@ extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream
     }
     ok = ok && hipMalloc((void **)&b->table, sizeof(RunDev) * (size_t)cfg->max_runs) == hipSuccess;
     ok = ok && hipMalloc((void **)&b->items_dev, sizeof(WorkItem) * (size_t)b->item_cap) == hipSuccess;
-    ok = ok && hipMalloc((void **)&b->wg_dev, sizeof(int32_t) * (size_t)(b->grid + 1)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->wg_dev, sizeof(int32_t) * (size_t)(b->grid_max + 1)) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&b->items_host, sizeof(WorkItem) * (size_t)b->item_cap) == hipSuccess;
-    ok = ok && hipHostMalloc((void **)&b->wg_host, sizeof(int32_t) * (size_t)(b->grid + 1)) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&b->wg_host, sizeof(int32_t) * (size_t)(b->grid_max + 1)) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         pic_batch_destroy(b);
@@ -855,7 +978,7 @@ extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, co
     fill_constants(r);
     carve(r);
     r->host.step_target = nsteps;
-    r->grid = single_run_grid(r, device_info());
+    r->grid = single_run_grid(r, r->shape, device_info().cus);
     st = upload_particles(r, x0, v_mhalf);
     if (st == PIC_OK) st = init_device_state(r);
     if (st != PIC_OK) {
@@ -880,22 +1003,87 @@ extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, co
     return PIC_OK;
 }
 
-extern "C" pic_status pic_batch_step(pic_batch *b, int64_t nsteps) {
-    pic_status st = batch_check(b);
-    if (st != PIC_OK) return st;
-    if (nsteps < 0) return fail(PIC_EINVAL, "nsteps must be >= 0");
+namespace {
+
+// Launch shape of the batch's particle pass for the current membership:
+// cached or tuned per size class (largest grid, total particles); tuning
+// runs particle passes on the members' own state and restores it.
+pic_status batch_choose_shape(pic_batch *b) {
+    if (b->shape_forced || !b->autotune) return PIC_OK;
+    int64_t total = 0;
+    std::vector<pic_run *> live;
+    for (auto &kv : b->members)
+        if (kv.second.launch_done > b->launches) {
+            total += kv.second.run->p.np;
+            live.push_back(kv.second.run);
+        }
+    if (live.empty()) return PIC_OK;
+    const std::string key = tune_key("batch", PIC_FP32, b->cfg.ng_max, total);
+    if (key == b->tuned_key) return PIC_OK;
+    LaunchShape shape = b->shape;
+    if (!tune_lookup(key, &shape)) {
+        size_t bytes = 0;
+        for (pic_run *r : live) bytes += 2 * (size_t)r->p.np * r->lay.esize;
+        char *tmp = nullptr;
+        if (hipMalloc((void **)&tmp, bytes) != hipSuccess)
+            return fail(PIC_ENOMEM, "autotune scratch of %zu bytes", bytes);
+        pic_status st = PIC_OK;
+        size_t off = 0;
+        for (pic_run *r : live) {
+            if (st == PIC_OK) st = save_particles(r, tmp + off, false);
+            off += 2 * (size_t)r->p.np * r->lay.esize;
+        }
+        hipError_t te = hipSuccess;
+        if (st == PIC_OK) {
+            te = tune_shapes(key, PIC_FP32, b->stream,
+                             [b](const LaunchShape &s) {
+                                 b->shape = s;
+                                 b->grid = b->cus * step_occupancy(s, b->cfg.ng_max, PIC_FP32);
+                                 if (rebuild_schedule(b) != PIC_OK) return hipErrorInvalidValue;
+                                 return launch_particles(b->table, b->items_dev, b->wg_dev, b->grid, s,
+                                                         b->cfg.ng_max, PIC_FP32, 0, b->stream);
+                             },
+                             &shape);
+            off = 0;
+            for (pic_run *r : live) {
+                pic_status rs = save_particles(r, tmp + off, true);
+                if (st == PIC_OK) st = rs;
+                off += 2 * (size_t)r->p.np * r->lay.esize;
+            }
+        }
+        hipError_t se = hipStreamSynchronize(b->stream);
+        (void)hipFree(tmp);
+        if (st != PIC_OK) return st;
+        if (te != hipSuccess) return fail(PIC_EDEVICE, "batch autotune: %s", hipGetErrorString(te));
+        if (se != hipSuccess) return fail(PIC_EDEVICE, "batch autotune: %s", hipGetErrorString(se));
+    }
+    b->shape = shape;
+    HIP_TRY(step_prepare(b->shape, PIC_FP32));
+    b->grid = b->cus * step_occupancy(b->shape, b->cfg.ng_max, PIC_FP32);
+    b->tuned_key = key;
+    if (b->graph) {                                   // captured with the old shape
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return PIC_OK;
+}
+
+// Advance the batch by up to `nsteps` launches.  With `evs`, no graph is used
+// and each launch is bracketed by a StepEvents entry appended to *evs.
+pic_status batch_advance(pic_batch *b, int64_t nsteps, std::vector<StepEvents> *evs) {
     int64_t left = nsteps;
     while (left > 0) {
         const int64_t nc = next_completion(b);
         if (nc == INT64_MAX) break;                      // nothing left to run
         if (b->dirty) {
-            st = rebuild_schedule(b);
+            pic_status st = batch_choose_shape(b);
+            if (st == PIC_OK) st = rebuild_schedule(b);
             if (st != PIC_OK) return st;
         }
         int64_t k = std::min(left, nc - b->launches);    // launches before membership changes
         const int G = b->cfg.graph_steps;
-        if (G > 1 && k >= G) {
-            st = ensure_graph(b);
+        if (!evs && G > 1 && k >= G) {
+            pic_status st = ensure_graph(b);
             if (st != PIC_OK) return st;
             while (k >= G) {
                 HIP_TRY(hipGraphLaunch(b->graph, b->stream));
@@ -905,14 +1093,69 @@ extern "C" pic_status pic_batch_step(pic_batch *b, int64_t nsteps) {
             }
         }
         for (; k > 0; --k, --left) {
-            st = batch_launch_one(b);
-            if (st != PIC_OK) return st;
+            const StepEvents *ev = nullptr;
+            if (evs) {
+                StepEvents e{};
+                HIP_TRY(hipEventCreate(&e.e0));
+                HIP_TRY(hipEventCreate(&e.e1));
+                HIP_TRY(hipEventCreate(&e.e2));
+                evs->push_back(e);
+                ev = &evs->back();
+            }
+            hipError_t le = launch_step(b->table, b->items_dev, b->wg_dev, b->grid, b->shape,
+                                        b->cfg.ng_max, PIC_FP32, 0, b->cfg.max_runs, b->stream, ev);
+            if (le != hipSuccess) {
+                b->error = true;
+                return fail(PIC_EDEVICE, "batch step launch failed: %s", hipGetErrorString(le));
+            }
             b->launches += 1;
         }
         if (b->launches >= nc) b->dirty = true;          // some run just finished
-        st = add_mark(b);
+        pic_status st = add_mark(b);
         if (st != PIC_OK) return st;
     }
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" pic_status pic_batch_step(pic_batch *b, int64_t nsteps) {
+    pic_status st = batch_check(b);
+    if (st != PIC_OK) return st;
+    if (nsteps < 0) return fail(PIC_EINVAL, "nsteps must be >= 0");
+    return batch_advance(b, nsteps, nullptr);
+}
+
+extern "C" pic_status pic_batch_step_profiled(pic_batch *b, int64_t nsteps, double *ms_particle,
+                                              double *ms_solve) {
+    pic_status st = batch_check(b);
+    if (st != PIC_OK) return st;
+    if (nsteps < 1) return fail(PIC_EINVAL, "nsteps must be >= 1");
+    std::vector<StepEvents> evs;
+    evs.reserve((size_t)nsteps);
+    st = batch_advance(b, nsteps, &evs);
+    hipError_t se = hipStreamSynchronize(b->stream);
+    double a = 0, c = 0;
+    for (auto &e : evs) {
+        float t1 = 0, t2 = 0;
+        if (st == PIC_OK && se == hipSuccess) {
+            (void)hipEventElapsedTime(&t1, e.e0, e.e1);
+            (void)hipEventElapsedTime(&t2, e.e1, e.e2);
+        }
+        a += t1;
+        c += t2;
+        (void)hipEventDestroy(e.e0);
+        (void)hipEventDestroy(e.e1);
+        (void)hipEventDestroy(e.e2);
+    }
+    if (st != PIC_OK) return st;
+    if (se != hipSuccess) {
+        b->error = true;
+        return fail(PIC_EDEVICE, "device error: %s", hipGetErrorString(se));
+    }
+    if (evs.empty()) return fail(PIC_ESTATE, "no unfinished runs to step");
+    if (ms_particle) *ms_particle = a / (double)evs.size();
+    if (ms_solve) *ms_solve = c / (double)evs.size();
     return PIC_OK;
 }
 

@@ -18,6 +18,7 @@ uniform ion background of density 1, periodic domain of length L.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 from typing import Callable, List, Optional, Tuple
 
@@ -50,24 +51,45 @@ def splitmix64(seed: int, stream: int, start: int, n: int) -> np.ndarray:
         return _mix(base + idx * _GAMMA)
 
 
+_POOL = None
+
+
+def _chunks(n: int, fill: Callable[[int, int], None]) -> None:
+    """Run fill(a, b) over [0, n) in chunks, on a thread pool for large n
+    (each element depends only on its index, so the result does not depend
+    on the number of threads)."""
+    global _POOL
+    spans = [(a, min(n, a + _CHUNK)) for a in range(0, n, _CHUNK)]
+    if len(spans) <= 1:
+        for a, b in spans:
+            fill(a, b)
+        return
+    if _POOL is None:
+        from concurrent.futures import ThreadPoolExecutor
+        _POOL = ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1))
+    list(_POOL.map(lambda ab: fill(*ab), spans))
+
+
 def uniform(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
     """Uniform doubles in [0, 1) (53-bit), generated in chunks to bound memory."""
     out = np.empty(n, dtype=np.float64)
-    for a in range(0, n, _CHUNK):
-        b = min(n, a + _CHUNK)
+
+    def fill(a, b):
         r = splitmix64(seed, stream, start + a, b - a)
         out[a:b] = (r >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    _chunks(n, fill)
     return out
 
 
 def normal(seed: int, stream: int, n: int) -> np.ndarray:
     """Standard normal deviates by Box-Muller from two uniform streams."""
     out = np.empty(n, dtype=np.float64)
-    for a in range(0, n, _CHUNK):
-        b = min(n, a + _CHUNK)
+
+    def fill(a, b):
         u1 = uniform(seed, stream, b - a, start=a)
         u2 = uniform(seed, stream + 1, b - a, start=a)
         out[a:b] = np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * math.pi * u2)
+    _chunks(n, fill)
     return out
 
 

@@ -25,7 +25,7 @@ PIC_FLAG_NONFINITE, PIC_FLAG_MULTIWRAP = 1, 2
 
 SYMBOLS = (
     "pic_last_error", "pic_version", "pic_footprint", "pic_create", "pic_step", "pic_step_graph",
-    "pic_diagnostics", "pic_read_particles", "pic_read_raw", "pic_read_grid", "pic_read_history",
+    "pic_step_profiled", "pic_batch_step_profiled", "pic_diagnostics", "pic_read_particles", "pic_read_raw", "pic_read_grid", "pic_read_history",
     "pic_destroy", "pic_batch_create", "pic_batch_admit", "pic_batch_step", "pic_batch_poll",
     "pic_batch_run", "pic_batch_release", "pic_batch_usage", "pic_batch_destroy",
 )
@@ -90,6 +90,8 @@ def load(path: str = LIB_PATH):
         "pic_create": [P, dptr, dptr, vp, sz, vp, C.POINTER(vp)],
         "pic_step": [vp, i64],
         "pic_step_graph": [vp, i64, i32],
+        "pic_step_profiled": [vp, i64, dptr, dptr],
+        "pic_batch_step_profiled": [vp, i64, dptr, dptr],
         "pic_diagnostics": [vp, C.POINTER(pic_diag), vp, vp, i32],
         "pic_read_particles": [vp, vp, vp, i64],
         "pic_read_raw": [vp, vp, vp, i64],
@@ -160,6 +162,19 @@ def pic_step(run, nsteps: int) -> None:
 
 def pic_step_graph(run, nsteps: int, graph_steps: int) -> None:
     _check(load().pic_step_graph(run, int(nsteps), int(graph_steps)))
+
+
+def pic_step_profiled(run, nsteps: int) -> Tuple[float, float]:
+    """Mean (particle-pass, solve) launch durations in ms over `nsteps` steps."""
+    a, b = C.c_double(0), C.c_double(0)
+    _check(load().pic_step_profiled(run, int(nsteps), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def pic_batch_step_profiled(batch, nsteps: int) -> Tuple[float, float]:
+    a, b = C.c_double(0), C.c_double(0)
+    _check(load().pic_batch_step_profiled(batch, int(nsteps), C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def pic_diagnostics(run, ng: int = 0) -> Tuple[dict, Optional[np.ndarray], Optional[np.ndarray]]:

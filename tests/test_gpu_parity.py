@@ -329,3 +329,23 @@ def test_admission_under_a_small_budget_and_release():
             u, w = r.raw()
         np.testing.assert_array_equal(results[k][0], u)
         np.testing.assert_array_equal(results[k][1], w)
+
+
+def test_results_do_not_depend_on_the_launch_shape(monkeypatch):
+    """Tiles and summation orders are fixed by the run, so every launch shape
+    the autotuner may pick gives bit-identical state, grid and history."""
+    spec = I.warm_two_stream_large(seed=21, np_=200_003, ng=256, nsteps=12, L=0.032 * 256)
+    x, v = spec.particles()
+    ref = None
+    for block, unroll in [(1024, 1), (512, 2), (256, 4), (1024, 4)]:
+        monkeypatch.setenv("PIC1D_BLOCK", str(block))
+        monkeypatch.setenv("PIC1D_UNROLL", str(unroll))
+        run, p = make_run(spec, history=spec.nsteps, x=x, v=v)
+        with run:
+            run.step(spec.nsteps)
+            got = (*run.raw(), run.grid()[0], run.grid()[1], run.history())
+        if ref is None:
+            ref = got
+        else:
+            for a, b in zip(ref, got):
+                np.testing.assert_array_equal(a, b)
