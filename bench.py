@@ -9,8 +9,10 @@ L = 0.032 Ng, two warm beams, dt = 0.1), stepped by one persistent particle
 launch plus one solve launch per step from a captured HIP graph.  The same
 runs are also stepped one after another on the plain per-run path (ordinary
 launches sized to each run), and a single large warm two-stream run
-(Np = 2^26, Ng = 4096) is timed for reference.  `--serving` adds the
-continuous-batching serving measurement (p50/p99 run latency).
+(Np = 2^26, Ng = 4096) is timed for reference.  Then the serving load:
+Poisson arrivals at 50 runs/s of runs drawn as the ensemble with 100..2000
+steps, admitted by HBM footprint under a 200 GB budget (and again under
+256 MiB), reporting p50/p99 completion latency and aggregate particle-steps/s.
 
 Prints ONE JSON line.  Inputs are seeded and synthetic; particle state is
 resident in HBM before the timed region starts.
@@ -50,8 +52,11 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving", action="store_true", help="also run the serving load")
-    ap.add_argument("--serving-runs", type=int, default=300)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving load")
+    ap.add_argument("--serving-runs", type=int, default=1000)
+    ap.add_argument("--serving-rate", type=float, default=50.0)
+    ap.add_argument("--serving-tight-runs", type=int, default=300,
+                    help="requests replayed under a 256 MiB budget (0: skip)")
     return ap.parse_args()
 
 
@@ -196,10 +201,22 @@ def main():
 
     # ------------------------------------------------------------- serving
     serving = None
-    if args.serving:
+    if not args.no_serving:
         from paper_1108_1954_amd import serve
-        serving = serve.serve_load(nruns=args.serving_runs, np_scale=args.np_scale, stream=stream)
+        t0 = time.perf_counter()
+        reqs = serve.make_requests(args.serving_runs, rate=args.serving_rate, np_scale=args.np_scale)
+        log(f"serving: {len(reqs)} requests generated in {time.perf_counter() - t0:.1f} s")
+        serving = serve.serve_load(rate=args.serving_rate, budget=200 << 30, requests=reqs)
+        serving["workload"] = (f"Poisson arrivals {args.serving_rate:g}/s, {len(reqs)} runs drawn as the "
+                               "ensemble with steps U{100..2000}, 200 GB budget")
         log(f"serving: {serving}")
+        if args.serving_tight_runs > 0:
+            tight = serve.serve_load(rate=args.serving_rate, budget=256 << 20,
+                                     requests=reqs[:args.serving_tight_runs])
+            tight["workload"] = f"first {args.serving_tight_runs} requests of the same load, 256 MiB budget"
+            serving["tight_budget"] = tight
+            log(f"serving (256 MiB): {tight}")
+        del reqs
 
     # --------------------------------------------------------- CPU baseline
     cpu = None

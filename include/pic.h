@@ -17,7 +17,9 @@
  *      (Sec. 2.2), solved exactly with zero-mean potential.
  *
  * Numerics.  Particle state and push in FP32 (PIC_FP32) or FP64 (PIC_FP64).
- * Internally a particle is stored as u = x/dx in [0, ng) and w = v dt/dx.
+ * A particle is u = x/dx in [0, ng) and w = v dt/dx; the engine stores
+ * s = u + 1/2 (the exact same number shifted, so that the cell index is
+ * floor(s - 1) with ghost nodes at both ends of its tables).
  * The deposit is exact fixed point: with U = floor(u 2^32) (exact, from the
  * bits of u), j = floor((U - 2^31) / 2^32) and F = U - 2^31 - j 2^32, node
  * j mod ng receives 2^32 - F and node j+1 mod ng receives F as int64, so the
@@ -185,9 +187,15 @@ typedef struct pic_batch_config {
 
 pic_status pic_batch_create(const pic_batch_config *cfg, void *stream, pic_batch **out);
 
-/* Admit a run that will take `nsteps` steps.  PIC_EBUDGET if its footprint
- * does not fit the arena now (nothing is changed; retry after releases).
- * The initial deposit and solve are enqueued immediately. */
+/* Admit a run that will take `nsteps` steps from host x0[np], v_mhalf[np]
+ * (as pic_create; FP32 state only, ng <= ng_max).  PIC_EBUDGET if its
+ * footprint does not fit the arena or the run table is full now (nothing is
+ * changed; retry after releases).  Asynchronous: the particles are converted
+ * into pinned staging memory before the call returns (the caller's arrays
+ * are free again), then upload, grid clearing and the initial deposit and
+ * solve are enqueued on the batch stream; the host does not wait.  The run
+ * joins the next pic_batch_step launch.  A failure after work was enqueued
+ * puts the batch in the error state (PIC_EDEVICE, then PIC_ESTATE). */
 pic_status pic_batch_admit(pic_batch *b, const pic_params *params, const double *x0,
                            const double *v_mhalf, int64_t nsteps, int64_t *run_id);
 
@@ -208,7 +216,11 @@ pic_status pic_batch_poll(pic_batch *b, int64_t *done_ids, int32_t cap, int32_t 
  * read/diagnostic calls above work on it (pic_step/pic_destroy do not). */
 pic_status pic_batch_run(pic_batch *b, int64_t run_id, pic_run **view);
 
-/* Free a run's arena space (waits for the batch's queued work first). */
+/* Retire a run: its table slot and arena space become free for later
+ * admissions at once.  Asynchronous and safe while work is queued: reuse is
+ * ordered after that work on the batch stream.  Its pic_run view and its
+ * results are gone; read them (pic_diagnostics etc. on the view) before.
+ * Releasing an unfinished run stops it. */
 pic_status pic_batch_release(pic_batch *b, int64_t run_id);
 
 /* Bytes of the arena in use / free, and runs admitted and not released. */

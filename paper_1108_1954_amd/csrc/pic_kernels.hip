@@ -1,13 +1,17 @@
 // Device kernels of the 1D electrostatic PIC step (gfx950).
 //
-// One launch of step_kernel advances every scheduled run by one step:
-//   gather E^n (Sec. 2.3) -> kick (Sec. 2.1) -> drift + periodic wrap
-//   (Sec. 2.1) -> exact fixed-point charge deposit (Sec. 2.3) into a
-//   workgroup-private int64 grid in LDS -> merge into the run's global grid
-//   with 64-bit atomics -> the last workgroup to finish a run solves the
-//   periodic Poisson problem and forms the central-difference field
-//   (Sec. 2.2) in FP64, writing E^{n+1} and the step's diagnostics.
-//
+// A step is two launches on one stream:
+//   step_kernel (particle pass): gather E^n (Sec. 2.3) -> kick (Sec. 2.1) ->
+//     drift + periodic wrap (Sec. 2.1) -> exact fixed-point charge deposit
+//     (Sec. 2.3) into a workgroup-private int64 grid in LDS -> merge into the
+//     run's global grid with 64-bit atomics, plus per-tile FP64 partial sums
+//     of the diagnostics;
+//   solve_kernel (one workgroup per run): the periodic Poisson problem and the
+//     central-difference field (Sec. 2.2) in FP64, writing E^{n+1}, the gather
+//     table for the next step and the step's diagnostics.
+// The kernel boundary orders the merge before the solve, so no device-wide
+// fence or completion counter is needed.
+
 // Particles are independent within a step, so they are sharded by index
 // (tiles of `tile` particles, one tile per wavefront at a time) instead of by
 // domain; the grid reduction replaces the paper's ghost-cell exchange and the
@@ -493,7 +497,8 @@ __global__ __launch_bounds__(BLOCK, (UNROLL >= 4 ? 4 : 6)) void step_kernel(
             chunk = blockIdx.x;
         }
         RunDev *R = runs + r;
-        if (te <= tb || R->step >= R->step_target || R->ng > ng_lds) continue;
+        // the prologue (initial deposit) runs whatever the step target, even 0
+        if (te <= tb || (PUSH && R->step >= R->step_target) || R->ng > ng_lds) continue;
         process_chunk<T, BLOCK, UNROLL, PUSH>(R, tb, te, chunk, r != prev_run, Sl, Et);
         prev_run = r;
     }
@@ -506,7 +511,7 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(RunDev *runs, int 
     __shared__ double red[kSolveThreads / 64];
     __shared__ long long redi[kSolveThreads / 64];
     RunDev *R = runs + blockIdx.x;
-    if (R->step >= R->step_target) return;
+    if (!prologue && R->step >= R->step_target) return;
     solve_run(R, D, red, redi, prologue != 0);
 }
 

@@ -162,6 +162,11 @@ struct pic_run {
     bool owns_dev = false;
     bool error = false;
     bool batch_member = false;
+    // Batch members: reads go through the batch's own non-blocking stream,
+    // and a run reported complete (settled) is read without waiting for the
+    // batch's queued launches, which no longer touch it.
+    hipStream_t io_stream = nullptr;
+    bool settled = false;
     LaunchShape shape;
     int grid = 1;
     double Q = 0, m = 0, dx = 0;
@@ -235,52 +240,64 @@ void carve(pic_run *r) {
     h.sort_hist = nullptr;
 }
 
-// Convert host FP64 particles to engine units and upload them: the stored
-// position is s = x/dx + 1/2 in [1/2, ng + 1/2) (rounded once to the state
-// precision; a value that rounds up to ng + 1/2 is the same point as x = 0)
-// and the velocity w = v dt/dx.
-pic_status upload_particles(pic_run *r, const double *x0, const double *v) {
+// Convert host FP64 particles to engine units: the stored position is
+// s = x/dx + 1/2 in [1/2, ng + 1/2) (rounded once to the state precision; a
+// value that rounds up to ng + 1/2 is the same point as x = 0) and the
+// velocity w = v dt/dx.  `u` and `w` receive np elements of the state type.
+void convert_particles(const pic_run *r, const double *x0, const double *v, void *u, void *w) {
     const pic_params &p = r->p;
     const double wscale = p.dt / r->dx;
     const size_t n = (size_t)p.np;
     if (p.precision == PIC_FP32) {
-        std::vector<float> u(n), w(n);
+        float *uo = (float *)u, *wo = (float *)w;
         const float hi = (float)p.ng + 0.5f;
         for (size_t i = 0; i < n; ++i) {
             float si = (float)(x0[i] / r->dx + 0.5);
             if (!(si < hi)) si = 0.5f;
-            u[i] = si;
-            w[i] = (float)(v[i] * wscale);
+            uo[i] = si;
+            wo[i] = (float)(v[i] * wscale);
         }
-        HIP_TRY(hipMemcpyAsync(r->host.u, u.data(), n * 4, hipMemcpyHostToDevice, r->stream));
-        HIP_TRY(hipMemcpyAsync(r->host.w, w.data(), n * 4, hipMemcpyHostToDevice, r->stream));
-        HIP_TRY(hipStreamSynchronize(r->stream));
     } else {
-        std::vector<double> u(n), w(n);
+        double *uo = (double *)u, *wo = (double *)w;
         const double hi = (double)p.ng + 0.5;
         for (size_t i = 0; i < n; ++i) {
             double si = x0[i] / r->dx + 0.5;
             if (!(si < hi)) si = 0.5;
-            u[i] = si;
-            w[i] = v[i] * wscale;
+            uo[i] = si;
+            wo[i] = v[i] * wscale;
         }
-        HIP_TRY(hipMemcpyAsync(r->host.u, u.data(), n * 8, hipMemcpyHostToDevice, r->stream));
-        HIP_TRY(hipMemcpyAsync(r->host.w, w.data(), n * 8, hipMemcpyHostToDevice, r->stream));
-        HIP_TRY(hipStreamSynchronize(r->stream));
     }
+}
+
+// Convert and upload a single run's particles (synchronous).
+pic_status upload_particles(pic_run *r, const double *x0, const double *v) {
+    const size_t bytes = (size_t)r->p.np * r->lay.esize;
+    std::vector<char> u(bytes), w(bytes);
+    convert_particles(r, x0, v, u.data(), w.data());
+    HIP_TRY(hipMemcpyAsync(r->host.u, u.data(), bytes, hipMemcpyHostToDevice, r->stream));
+    HIP_TRY(hipMemcpyAsync(r->host.w, w.data(), bytes, hipMemcpyHostToDevice, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
     return PIC_OK;
 }
 
-// Zero the grids, publish the descriptor and run the prologue (deposit of
-// x^0 and solve for E^0) for a single run.
-pic_status init_device_state(pic_run *r) {
+// Queue, on the run's stream: zero the grids, publish the descriptor from
+// `desc` (host memory that stays valid until the copy has run) and run the
+// prologue (deposit of x^0 and solve for E^0).  Nothing waits.
+pic_status queue_device_init(pic_run *r, const RunDev *desc) {
     HIP_TRY(hipMemsetAsync(r->host.S, 0, (size_t)r->p.ng * 8, r->stream));
     HIP_TRY(hipMemsetAsync(r->host.S_last, 0, (size_t)r->p.ng * 8, r->stream));
     HIP_TRY(hipMemsetAsync(r->host.tile_part, 0, (size_t)r->lay.ntiles * kPartCols * 8, r->stream));
-    HIP_TRY(hipMemcpyAsync(r->dev, &r->host, sizeof(RunDev), hipMemcpyHostToDevice, r->stream));
+    HIP_TRY(hipMemcpyAsync(r->dev, desc, sizeof(RunDev), hipMemcpyHostToDevice, r->stream));
     HIP_TRY(step_prepare(r->shape, r->p.precision));
     HIP_TRY(launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng, r->p.precision, 1,
                         1, r->stream));
+    return PIC_OK;
+}
+
+// Device state of a single run, synchronously.
+pic_status init_device_state(pic_run *r) {
+    pic_status st = queue_device_init(r, &r->host);
+    if (st != PIC_OK) return st;
     HIP_TRY(hipStreamSynchronize(r->stream));
     return PIC_OK;
 }
@@ -385,12 +402,20 @@ pic_status capture_graph(F launch, int count, hipGraphExec_t *exec) {
 }
 
 pic_status sync_run(pic_run *r) {
+    if (r->settled) return PIC_OK;
     hipError_t e = hipStreamSynchronize(r->stream);
     if (e != hipSuccess) {
         r->error = true;
         return fail(PIC_EDEVICE, "device error: %s", hipGetErrorString(e));
     }
     return PIC_OK;
+}
+
+// Device-to-host copy for the read calls (after sync_run).
+hipError_t dev_read(const pic_run *r, void *dst, const void *src, size_t bytes) {
+    if (!r->io_stream) return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, r->io_stream);
+    return e != hipSuccess ? e : hipStreamSynchronize(r->io_stream);
 }
 
 }  // namespace
@@ -555,7 +580,7 @@ extern "C" pic_status pic_diagnostics(pic_run *r, pic_diag *diag, double *rho_ou
     st = sync_run(r);
     if (st != PIC_OK) return st;
     RunDev d;
-    HIP_TRY(hipMemcpy(&d, r->dev, sizeof d, hipMemcpyDeviceToHost));
+    HIP_TRY(dev_read(r, &d, r->dev, sizeof d));
     diag->step = d.step;
     diag->time = (double)d.step * r->p.dt;
     diag->kinetic = d.kinetic_now;
@@ -567,12 +592,12 @@ extern "C" pic_status pic_diagnostics(pic_run *r, pic_diag *diag, double *rho_ou
     diag->pad_ = 0;
     if (rho_out) {
         std::vector<unsigned long long> S((size_t)r->p.ng);
-        HIP_TRY(hipMemcpy(S.data(), r->host.S_last, S.size() * 8, hipMemcpyDeviceToHost));
+        HIP_TRY(dev_read(r, S.data(), r->host.S_last, S.size() * 8));
         const double qdx = r->Q / r->dx;
         for (int g = 0; g < r->p.ng; ++g)
             rho_out[g] = r->p.rho0 + qdx * ((double)S[g] / 4294967296.0);
     }
-    if (E_out) HIP_TRY(hipMemcpy(E_out, r->host.E64, (size_t)r->p.ng * 8, hipMemcpyDeviceToHost));
+    if (E_out) HIP_TRY(dev_read(r, E_out, r->host.E64, (size_t)r->p.ng * 8));
     return PIC_OK;
 }
 
@@ -585,7 +610,7 @@ extern "C" pic_status pic_read_raw(pic_run *r, void *u, void *w, int64_t cap) {
     const size_t n = (size_t)r->p.np;
     const size_t bytes = n * r->lay.esize;
     if (u) {
-        HIP_TRY(hipMemcpy(u, r->host.u, bytes, hipMemcpyDeviceToHost));
+        HIP_TRY(dev_read(r, u, r->host.u, bytes));
         // stored s = u + 1/2 with s >= 1/2: s - 1/2 is exact in either precision
         if (r->p.precision == PIC_FP32) {
             float *f = (float *)u;
@@ -595,7 +620,7 @@ extern "C" pic_status pic_read_raw(pic_run *r, void *u, void *w, int64_t cap) {
             for (size_t i = 0; i < n; ++i) d[i] -= 0.5;
         }
     }
-    if (w) HIP_TRY(hipMemcpy(w, r->host.w, bytes, hipMemcpyDeviceToHost));
+    if (w) HIP_TRY(dev_read(r, w, r->host.w, bytes));
     return PIC_OK;
 }
 
@@ -632,9 +657,9 @@ extern "C" pic_status pic_read_grid(pic_run *r, int64_t *S, double *E, float *Eh
     st = sync_run(r);
     if (st != PIC_OK) return st;
     const size_t ng = (size_t)r->p.ng;
-    if (S) HIP_TRY(hipMemcpy(S, r->host.S_last, ng * 8, hipMemcpyDeviceToHost));
-    if (E) HIP_TRY(hipMemcpy(E, r->host.E64, ng * 8, hipMemcpyDeviceToHost));
-    if (Ehat) HIP_TRY(hipMemcpy(Ehat, r->host.Ehat, ng * 4, hipMemcpyDeviceToHost));
+    if (S) HIP_TRY(dev_read(r, S, r->host.S_last, ng * 8));
+    if (E) HIP_TRY(dev_read(r, E, r->host.E64, ng * 8));
+    if (Ehat) HIP_TRY(dev_read(r, Ehat, r->host.Ehat, ng * 4));
     return PIC_OK;
 }
 
@@ -644,15 +669,15 @@ extern "C" pic_status pic_read_history(pic_run *r, int64_t first, int64_t count,
     st = sync_run(r);
     if (st != PIC_OK) return st;
     RunDev d;
-    HIP_TRY(hipMemcpy(&d, r->dev, sizeof d, hipMemcpyDeviceToHost));
+    HIP_TRY(dev_read(r, &d, r->dev, sizeof d));
     const int64_t avail = std::min<int64_t>(d.step, r->p.history_cap);
     if (first < 0 || count < 0 || first + count > avail)
         return fail(PIC_EINVAL, "history rows [%lld, %lld) outside the %lld available",
                     (long long)first, (long long)(first + count), (long long)avail);
     if (count == 0) return PIC_OK;
     if (!rows) return fail(PIC_EINVAL, "rows is NULL");
-    HIP_TRY(hipMemcpy(rows, r->host.hist + (size_t)first * kHistCols,
-                      (size_t)count * kHistCols * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(dev_read(r, rows, r->host.hist + (size_t)first * kHistCols,
+                      (size_t)count * kHistCols * 8));
     return PIC_OK;
 }
 
@@ -727,14 +752,28 @@ struct Member {
     size_t off, bytes;     // arena span
     int64_t nsteps;        // steps requested
     int64_t launch_done;   // batch launch index after which the run is complete
+    int64_t admit_seq = 0; // completion mark recorded after its prologue
     bool reported = false;
 };
+
+// Pinned host buffer that carries one admission's converted particles and
+// descriptor to the device; reusable once `done` (recorded after the
+// copies) has completed.
+struct Staging {
+    char *host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+};
+
+constexpr size_t kStagingKeep = (size_t)1 << 30;   // idle pinned bytes kept for reuse
 
 }  // namespace
 
 struct pic_batch {
     pic_batch_config cfg{};
     hipStream_t stream = nullptr;
+    hipStream_t io_stream = nullptr;  // reads of members (non-blocking, default priority)
     char *arena_base = nullptr;
     bool owns_arena = false;
     Arena arena;
@@ -755,8 +794,18 @@ struct pic_batch {
     int64_t launches = 0;             // batch step launches issued
     bool dirty = true;                // work list needs a rebuild
     hipGraphExec_t graph = nullptr;
-    std::vector<std::pair<int64_t, hipEvent_t>> marks;   // (launch count, event)
+    // Completion marks: events recorded on the batch stream after launches
+    // and admissions, in order; `seq` numbers them.
+    struct Mark {
+        int64_t launches, seq;
+        hipEvent_t ev;
+    };
+    std::vector<Mark> marks;
+    int64_t mark_seq = 0;             // marks recorded
+    int64_t seq_complete = 0;         // marks known complete
     int64_t launches_complete = 0;
+    std::vector<Staging> staging;     // admission staging pool
+    RunDev *idle_host = nullptr;      // pinned idle descriptor (copied into released slots)
     bool error = false;
 };
 
@@ -853,23 +902,71 @@ pic_status add_mark(pic_batch *b) {
     hipEvent_t ev;
     HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(ev, b->stream));
-    b->marks.push_back({b->launches, ev});
+    b->marks.push_back({b->launches, ++b->mark_seq, ev});
     return PIC_OK;
 }
 
 void harvest_marks(pic_batch *b) {
     size_t k = 0;
     for (; k < b->marks.size(); ++k) {
-        hipError_t q = hipEventQuery(b->marks[k].second);
+        hipError_t q = hipEventQuery(b->marks[k].ev);
         if (q == hipErrorNotReady) break;
         if (q != hipSuccess) {
             b->error = true;
             break;
         }
-        b->launches_complete = std::max(b->launches_complete, b->marks[k].first);
-        (void)hipEventDestroy(b->marks[k].second);
+        b->launches_complete = std::max(b->launches_complete, b->marks[k].launches);
+        b->seq_complete = b->marks[k].seq;
+        (void)hipEventDestroy(b->marks[k].ev);
     }
     b->marks.erase(b->marks.begin(), b->marks.begin() + (long)k);
+}
+
+void reap_staging(pic_batch *b) {
+    for (Staging &g : b->staging)
+        if (g.busy && hipEventQuery(g.done) == hipSuccess) g.busy = false;
+}
+
+// Index of an idle staging buffer of at least `need` bytes, allocating one
+// (power-of-two size, >= 1 MiB) when none is free.  Idle buffers beyond
+// kStagingKeep bytes are returned to the system first.
+pic_status get_staging(pic_batch *b, size_t need, size_t *index) {
+    reap_staging(b);
+    size_t best = SIZE_MAX;
+    for (size_t i = 0; i < b->staging.size(); ++i) {
+        const Staging &g = b->staging[i];
+        if (!g.busy && g.bytes >= need && (best == SIZE_MAX || g.bytes < b->staging[best].bytes)) best = i;
+    }
+    if (best != SIZE_MAX) {
+        *index = best;
+        return PIC_OK;
+    }
+    size_t idle = 0;
+    for (const Staging &g : b->staging)
+        if (!g.busy) idle += g.bytes;
+    for (size_t i = 0; i < b->staging.size() && idle + need > kStagingKeep;) {
+        Staging &g = b->staging[i];
+        if (g.busy) {
+            ++i;
+            continue;
+        }
+        idle -= g.bytes;
+        (void)hipHostFree(g.host);
+        (void)hipEventDestroy(g.done);
+        b->staging.erase(b->staging.begin() + (long)i);
+    }
+    Staging g;
+    g.bytes = (size_t)1 << 20;
+    while (g.bytes < need) g.bytes <<= 1;
+    if (hipHostMalloc((void **)&g.host, g.bytes) != hipSuccess)
+        return fail(PIC_ENOMEM, "pinned staging buffer of %zu bytes", g.bytes);
+    if (hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(g.host);
+        return fail(PIC_EDEVICE, "event creation failed");
+    }
+    b->staging.push_back(g);
+    *index = b->staging.size() - 1;
+    return PIC_OK;
 }
 
 }  // namespace
@@ -912,6 +1009,8 @@ extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream
     ok = ok && hipHostMalloc((void **)&b->items_host, sizeof(WorkItem) * (size_t)b->item_cap) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&b->wg_host, sizeof(int32_t) * (size_t)(b->grid_max + 1)) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&b->idle_host, sizeof(RunDev)) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&b->io_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         pic_batch_destroy(b);
         return fail(PIC_ENOMEM, "batch allocation failed");
@@ -926,6 +1025,7 @@ extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream
             d = RunDev{};
             d.ng = 2;
         }
+        *b->idle_host = idle[0];
         if (hipMemcpy(b->table, idle.data(), sizeof(RunDev) * idle.size(), hipMemcpyHostToDevice) !=
             hipSuccess) {
             pic_batch_destroy(b);
@@ -969,6 +1069,7 @@ extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, co
     r->p = *params;
     r->lay = lay;
     r->stream = b->stream;
+    r->io_stream = b->io_stream;
     r->base = b->arena_base + off;
     r->batch_member = true;
     r->shape = b->shape;
@@ -978,13 +1079,39 @@ extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, co
     fill_constants(r);
     carve(r);
     r->host.step_target = nsteps;
-    r->grid = single_run_grid(r, r->shape, device_info().cus);
-    st = upload_particles(r, x0, v_mhalf);
-    if (st == PIC_OK) st = init_device_state(r);
+    r->grid = single_run_grid(r, r->shape, b->cus);
+    // Convert into pinned staging and queue upload, grid clearing,
+    // descriptor and prologue on the batch stream; the host does not wait.
+    const size_t desc_bytes = (sizeof(RunDev) + 255) & ~(size_t)255;
+    const size_t part_bytes = (size_t)params->np * lay.esize;
+    size_t gi = 0;
+    st = get_staging(b, desc_bytes + 2 * part_bytes, &gi);
+    if (st == PIC_OK) {
+        Staging &g = b->staging[gi];
+        convert_particles(r, x0, v_mhalf, g.host + desc_bytes, g.host + desc_bytes + part_bytes);
+        std::memcpy(g.host, &r->host, sizeof(RunDev));
+        g.busy = true;   // from here on the buffer may be read by queued copies
+        hipError_t e = hipMemcpyAsync(r->host.u, g.host + desc_bytes, part_bytes, hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->host.w, g.host + desc_bytes + part_bytes, part_bytes, hipMemcpyHostToDevice,
+                               b->stream);
+        if (e == hipSuccess) {
+            st = queue_device_init(r, (const RunDev *)g.host);
+            if (st != PIC_OK) e = hipErrorUnknown;
+        }
+        if (e == hipSuccess) e = hipEventRecord(g.done, b->stream);
+        if (e != hipSuccess) {
+            // work may be half queued on the stream: the batch cannot continue
+            b->error = true;
+            if (st == PIC_OK) st = fail(PIC_EDEVICE, "admission upload: %s", hipGetErrorString(e));
+        }
+    }
     if (st != PIC_OK) {
         std::string msg = g_err;
-        b->arena.release(off, lay.total);
-        b->free_slots.push_back(slot);
+        if (!b->error) {
+            b->arena.release(off, lay.total);
+            b->free_slots.push_back(slot);
+        }
         delete r;
         g_err = msg;
         return st;
@@ -997,6 +1124,13 @@ extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, co
     m.bytes = lay.total;
     m.nsteps = nsteps;
     m.launch_done = b->launches + nsteps;
+    st = add_mark(b);
+    if (st != PIC_OK) {
+        b->error = true;
+        delete r;
+        return st;
+    }
+    m.admit_seq = b->mark_seq;
     b->members[m.id] = m;
     b->dirty = true;
     *run_id = m.id;
@@ -1020,6 +1154,8 @@ pic_status batch_choose_shape(pic_batch *b) {
     if (live.empty()) return PIC_OK;
     const std::string key = tune_key("batch", PIC_FP32, b->cfg.ng_max, total);
     if (key == b->tuned_key) return PIC_OK;
+    const int old_grid = b->grid;              // what the captured graph launches
+    const LaunchShape old_shape = b->shape;
     LaunchShape shape = b->shape;
     if (!tune_lookup(key, &shape)) {
         size_t bytes = 0;
@@ -1061,7 +1197,10 @@ pic_status batch_choose_shape(pic_batch *b) {
     HIP_TRY(step_prepare(b->shape, PIC_FP32));
     b->grid = b->cus * step_occupancy(b->shape, b->cfg.ng_max, PIC_FP32);
     b->tuned_key = key;
-    if (b->graph) {                                   // captured with the old shape
+    // Tuning launches change the work list; the graph only has to go when
+    // the launch itself (shape or grid) changed.
+    b->dirty = true;
+    if (b->graph && (b->grid != old_grid || old_shape.block != shape.block || old_shape.unroll != shape.unroll)) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
@@ -1164,14 +1303,17 @@ extern "C" pic_status pic_batch_poll(pic_batch *b, int64_t *done_ids, int32_t ca
     if (st != PIC_OK) return st;
     if (!n_done || (cap > 0 && !done_ids)) return fail(PIC_EINVAL, "bad output arguments");
     harvest_marks(b);
+    reap_staging(b);
     if (b->error) return fail(PIC_EDEVICE, "device error in batch work");
     int32_t n = 0;
     for (auto &kv : b->members) {
         Member &m = kv.second;
-        if (m.reported || m.launch_done > b->launches_complete) continue;
+        // complete: its last launch and its admission (prologue) have run
+        if (m.reported || m.launch_done > b->launches_complete || m.admit_seq > b->seq_complete) continue;
         if (n >= cap) break;
         done_ids[n++] = m.id;
         m.reported = true;
+        m.run->settled = true;
     }
     *n_done = n;
     return PIC_OK;
@@ -1191,23 +1333,21 @@ extern "C" pic_status pic_batch_release(pic_batch *b, int64_t run_id) {
     if (!b) return fail(PIC_EINVAL, "batch is NULL");
     auto it = b->members.find(run_id);
     if (it == b->members.end()) return fail(PIC_EINVAL, "unknown run id %lld", (long long)run_id);
-    // The arena span may still be read by queued launches.
-    hipError_t e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) {
-        b->error = true;
-        return fail(PIC_EDEVICE, "device error: %s", hipGetErrorString(e));
-    }
+    if (b->error) return fail(PIC_ESTATE, "batch is in an error state after a device error");
+    // No wait: everything that reads the slot or the arena span was queued
+    // on the batch stream before anything that can reuse them.
     Member m = it->second;
     b->members.erase(it);
     // Park the slot: a descriptor whose step equals its target does no work.
-    RunDev idle{};
-    idle.step = 0;
-    idle.step_target = 0;
-    idle.ng = 2;
-    HIP_TRY(hipMemcpy(b->table + m.slot, &idle, sizeof idle, hipMemcpyHostToDevice));
+    hipError_t e = hipMemcpyAsync(b->table + m.slot, b->idle_host, sizeof(RunDev), hipMemcpyHostToDevice,
+                                  b->stream);
+    delete m.run;
+    if (e != hipSuccess) {
+        b->error = true;
+        return fail(PIC_EDEVICE, "release: %s", hipGetErrorString(e));
+    }
     b->arena.release(m.off, m.bytes);
     b->free_slots.push_back(m.slot);
-    delete m.run;
     b->dirty = true;
     return PIC_OK;
 }
@@ -1224,7 +1364,13 @@ extern "C" pic_status pic_batch_destroy(pic_batch *b) {
     if (!b) return PIC_OK;
     hipError_t e = hipStreamSynchronize(b->stream);
     for (auto &kv : b->members) delete kv.second.run;
-    for (auto &mk : b->marks) (void)hipEventDestroy(mk.second);
+    for (auto &mk : b->marks) (void)hipEventDestroy(mk.ev);
+    for (Staging &g : b->staging) {
+        (void)hipHostFree(g.host);
+        (void)hipEventDestroy(g.done);
+    }
+    if (b->idle_host) (void)hipHostFree(b->idle_host);
+    if (b->io_stream) (void)hipStreamDestroy(b->io_stream);
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
     if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->items_host) (void)hipHostFree(b->items_host);
