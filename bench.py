@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving load")
     ap.add_argument("--serving-runs", type=int, default=1000)
     ap.add_argument("--serving-rate", type=float, default=50.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run plain 1 GiB device copies (the reference for rocprofv3 byte counters)")
     ap.add_argument("--serving-tight-runs", type=int, default=300,
                     help="requests replayed under a 256 MiB budget (0: skip)")
     return ap.parse_args()
@@ -107,8 +109,26 @@ def cpu_baseline(spec, parts, budget_s=15.0):
                       f"{n} steps, {dt:.1f} s, single thread"}
 
 
+COPY_BYTES = 1 << 30
+
+
+def calibrate_copy(reps=4):
+    """Plain device-to-device copies of COPY_BYTES bytes: what FETCH_SIZE and
+    WRITE_SIZE read for one dispatch of these calibrates the counters."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_dispatch": COPY_BYTES, "dispatches": reps}), flush=True)
+
+
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the engine shards across GPUs "
               "only by design (see the design notes), no multi-GPU path is measured.", file=sys.stderr)

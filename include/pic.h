@@ -74,8 +74,8 @@ typedef struct pic_params {
     double  dt;           /* time step                                       */
     double  qm;           /* charge-to-mass ratio (electrons: -1)            */
     double  rho0;         /* ion background density (paper: 1)              */
-    int32_t sort_every;   /* cell sort every K steps; 0 = engine default, <0 never */
-    int32_t tile;         /* particles per tile (multiple of 256); 0 = default */
+    int32_t sort_every;   /* cell sort every K > 0 steps; <= 0 never (no room reserved) */
+    int32_t tile;         /* particles per tile (multiple of 1024); 0 = default */
     int64_t history_cap;  /* per-step history rows kept on the device        */
 } pic_params;
 
@@ -96,6 +96,7 @@ typedef struct pic_diag {
 
 #define PIC_FLAG_NONFINITE 1u  /* a non-finite position was reset to 0       */
 #define PIC_FLAG_MULTIWRAP 2u  /* a particle moved more than L in one step   */
+#define PIC_FLAG_SORT      4u  /* internal: a cell sort lost track of a slot  */
 
 /* One row per step n (0-based) of the per-step history:
  *   [0] KE^n  = (m/4) sum_p ((v^{n-1/2})^2 + (v^{n+1/2})^2)  (time-centred)
@@ -126,8 +127,18 @@ pic_status pic_create(const pic_params *params, const double *x0, const double *
                       void *dev_mem, size_t dev_bytes, void *stream, pic_run **out);
 
 /* Enqueue `nsteps` >= 0 steps (asynchronous; returns before they run).
- * Every `sort_every` steps the particles are first reordered by cell. */
+ * With sort_every = K > 0, the particles are reordered by cell (pic_sort)
+ * before steps K+1, 2K+1, ... counted from creation. */
 pic_status pic_step(pic_run *run, int64_t nsteps);
+
+/* Enqueue a cell sort now (asynchronous): a stable reorder of the
+ * particles by the cell of their left node, the locality step the engine
+ * also runs every sort_every steps.  Positions, velocities and every later
+ * result are unchanged as a multiset; only the storage order changes (and
+ * with it the per-tile summation order of the kinetic-energy and momentum
+ * diagnostics).  PIC_ESTATE if the run was created with sort_every <= 0
+ * (no room for the sort's alternate arrays). */
+pic_status pic_sort(pic_run *run);
 
 /* Same as pic_step but the steps are replayed from a captured HIP graph of
  * `graph_steps` launches (captured on first use, reused afterwards). */

@@ -72,6 +72,7 @@ def _bind(L):
     L.ora_deposit_plain.argtypes = [P, dp, dp]
     L.ora_deposit_fixed.argtypes = [C.c_int32, C.c_int64, dp, ip]
     L.ora_density_fixed.argtypes = [P, ip, dp]
+    L.ora_cell_order.argtypes = [C.c_int32, C.c_int64, dp, ip]
     L.ora_solve.argtypes = [P, dp, dp, C.c_void_p]
     L.ora_cg_paper.argtypes = [P, dp, C.c_int32, dp, dp]
     L.ora_cg_paper.restype = C.c_int32
@@ -116,6 +117,14 @@ def deposit_fixed(ng: int, u) -> np.ndarray:
     S = np.empty(ng, dtype=np.int64)
     lib().ora_deposit_fixed(int(ng), int(u.size), u, S)
     return S
+
+
+def cell_order(ng: int, u) -> np.ndarray:
+    """Stable permutation of particles by cell key (u = x/dx)."""
+    u = _f64(u)
+    perm = np.empty(u.size, dtype=np.int64)
+    lib().ora_cell_order(int(ng), int(u.size), u, perm)
+    return perm
 
 
 def density_fixed(p: Params, S) -> np.ndarray:

@@ -41,6 +41,8 @@
  *   R3 wrap: x <- x - L floor(x/L), so positions live in [0, L).
  *   R4 fixed-point deposit (the engine's exact-charge form): see
  *      ora_deposit_fixed.
+ *   R5 cell order (the engine's optional locality sort, not in the paper):
+ *      stable by the left stencil node; see ora_cell_order.
  *
  * Parity status: every function below is pinned by tests against brute force,
  * dense linear algebra, closed forms or physical invariants; none is marked
@@ -129,6 +131,39 @@ void ora_deposit_fixed(int32_t ng, int64_t np, const double *u, int64_t *S)
         S[wrap_index(j, ng)] += ((int64_t)1 << 32) - F;
         S[wrap_index(j + 1, ng)] += F;
     }
+}
+
+/* Cell key of a normalised position u = x/dx in [0, ng): the left node of
+ * its two-node stencil before wrapping, floor(u - 1/2) in [-1, ng-1]
+ * (Sec. 2.3, reading R1), shifted to [0, ng].  Values outside the range
+ * (not produced by a valid state) are clamped to the end keys. */
+static int64_t cell_key(int32_t ng, double u)
+{
+    double j = floor(u - 0.5);
+    if (j < -1.0)
+        j = -1.0;
+    if (j > (double)(ng - 1))
+        j = (double)(ng - 1);
+    return (int64_t)j + 1;
+}
+
+/* Stable order of the particles by cell key: perm[k] is the index of the
+ * particle that goes to position k, particles with equal keys keep their
+ * input order.  This is not a step of the paper's cycle (its loops visit the
+ * particles in any order and the result does not depend on it); it states
+ * what the engine's optional locality reordering produces.  A counting sort
+ * written out directly: count the keys, turn the counts into first
+ * positions, then place the particles in input order. */
+void ora_cell_order(int32_t ng, int64_t np, const double *u, int64_t *perm)
+{
+    int64_t *first = calloc((size_t)ng + 2, sizeof *first);
+    for (int64_t i = 0; i < np; ++i)
+        first[cell_key(ng, u[i]) + 1] += 1;
+    for (int32_t k = 1; k <= ng + 1; ++k)
+        first[k] += first[k - 1];
+    for (int64_t i = 0; i < np; ++i)
+        perm[first[cell_key(ng, u[i])]++] = i;
+    free(first);
 }
 
 /* Charge density from the fixed-point sums: rho_g = rho0 + (Q/dx) S_g 2^-32. */

@@ -27,13 +27,13 @@ struct RunDev {
     double *E64;                 // [ng] node field (FP64)
     double *tile_part;           // [ntiles][kPartCols]
     double *hist;                // [hist_cap][kHistCols]
-    uint32_t *sort_hist;         // [nsort_blocks][ng] per-block cell counts
+    void *sort_scratch;          // cell-sort count table and block sums, may be null
     int64_t np;
     int64_t hist_cap;
     int64_t step;                // steps completed
     int64_t step_target;         // no further steps once step == step_target
     int32_t ng;
-    int32_t tile;                // particles per tile (multiple of 256)
+    int32_t tile;                // particles per tile (multiple of kUnit)
     int32_t ntiles;
     int32_t precision;           // 0 = FP32 state, 1 = FP64 state
     uint32_t pad0_;
@@ -62,6 +62,20 @@ struct WorkItem {
     int32_t pad_;
 };
 
+// Work queue of a batched particle pass (device memory): workgroups take
+// items in list order through `next`; the last workgroup to find the queue
+// empty (counted in `done`) resets both to 0 for the next launch.
+struct WorkQueue {
+    uint32_t next;
+    uint32_t done;
+    uint32_t nitems;
+    uint32_t pad_;
+};
+
+// Particles per block unit: tile t of a run owns units t, t + ntiles, ...
+// Tiles are whole units.
+constexpr int kUnit = 1024;
+
 // Launch shape of the step kernel (chosen per run by the autotuner):
 // threads per workgroup and particle vectors per lane per iteration.
 struct LaunchShape {
@@ -72,8 +86,8 @@ struct LaunchShape {
 // Kernel launchers (pic_kernels.hip).  launch_step enqueues one step on
 // `stream` as two launches: the particle pass, then the field solve.
 //   items == nullptr: single run `runs[0]`, tiles split evenly over `grid`
-//   workgroups.  Otherwise workgroup b processes items[wg_begin[b] ..
-//   wg_begin[b+1]).
+//   workgroups.  Otherwise the workgroups take items[0 .. queue->nitems)
+//   through the queue.
 //   The solve launch has nsolve workgroups; workgroup b solves runs[b]
 //   (idle and finished runs return at once).
 //   prologue != 0: deposit + solve only (creation), no push.
@@ -82,12 +96,12 @@ struct LaunchShape {
 struct StepEvents {
     hipEvent_t e0, e1, e2;
 };
-hipError_t launch_step(RunDev *runs, const WorkItem *items, const int32_t *wg_begin,
+hipError_t launch_step(RunDev *runs, const WorkItem *items, WorkQueue *queue,
                        int grid, const LaunchShape &shape, int ng_lds, int precision, int prologue,
                        int nsolve, hipStream_t stream, const StepEvents *ev = nullptr);
 
 // The particle pass alone (used by the autotuner on saved state).
-hipError_t launch_particles(RunDev *runs, const WorkItem *items, const int32_t *wg_begin,
+hipError_t launch_particles(RunDev *runs, const WorkItem *items, WorkQueue *queue,
                             int grid, const LaunchShape &shape, int ng_lds, int precision,
                             int prologue, hipStream_t stream);
 
@@ -101,6 +115,22 @@ int step_occupancy(const LaunchShape &shape, int ng_lds, int precision);
 // Dynamic LDS of one workgroup: the int64 grid plus the gather table, each
 // with two ghost nodes.
 size_t step_lds_bytes(int precision, int ng_lds);
+
+// Cell sort (pic_sort.hip).  A run of np particles is split into nseg
+// segments of seg particles (nseg <= kMaxSortSegments); the count table has
+// (ng + 1) * nseg entries, scanned in blocks of nblk.
+constexpr int kMaxSortSegments = 1024;
+struct SortPlan {
+    int seg, nseg, nblk;
+    int64_t table_len;
+};
+SortPlan sort_plan(int64_t np, int ng);
+size_t sort_scratch_bytes(int64_t np, int ng);
+// Allow the scatter kernel its LDS (once, before any launch or capture).
+hipError_t sort_prepare();
+// Enqueue a stable sort of run R's particles by cell into its alternate
+// arrays, then swap the arrays in the descriptor (device side).
+hipError_t launch_sort(RunDev *R, int64_t np, int ng, int precision, void *scratch, hipStream_t stream);
 
 // Autotuner (pic_tune.hip).  tune_key names a size class; tune_lookup finds
 // a cached shape; tune_shapes times `launch(shape)` (one particle pass on

@@ -112,6 +112,43 @@ __device__ __forceinline__ void push(T &s, T &w, T Ep, T ngf, T hi, uint32_t &fl
     s = sn;
 }
 
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Add every lane's pair (2^32 - F at node j, F at node j + 1) to the LDS
+// grid.  When all 64 lanes have their left node at j0 or j0 + 1 (j0 the
+// first lane's; typical once particles are in cell order), the pairs are
+// summed across the wavefront first and one lane adds the node totals, so
+// 64 lanes do not serialise on the same LDS addresses.  Integer sums: the
+// grid gets exactly the same values either way.
+__device__ __forceinline__ void deposit_pair(int j, uint32_t F, unsigned long long *Sl) {
+    const int j0 = __builtin_amdgcn_readfirstlane(j);
+    const bool up = j == j0 + 1;
+    const unsigned long long act = __ballot(1);
+    if (act == ~0ull && __ballot(j == j0 || up) == act) {
+        const uint32_t F0 = up ? 0u : F, F1 = up ? F : 0u;
+        // 16-bit halves keep the 32-bit wavefront sums exact
+        const uint32_t s0lo = wave_sum_u32(F0 & 0xffffu), s0hi = wave_sum_u32(F0 >> 16);
+        const uint32_t s1lo = wave_sum_u32(F1 & 0xffffu), s1hi = wave_sum_u32(F1 >> 16);
+        const unsigned long long n1 = (unsigned long long)__popcll(__ballot(up));
+        if ((threadIdx.x & 63) == 0) {
+            const unsigned long long S0 = ((unsigned long long)s0hi << 16) + s0lo;
+            const unsigned long long S1 = ((unsigned long long)s1hi << 16) + s1lo;
+            unsigned long long *p = Sl + (j0 + 1);
+            atomicAdd(p, ((64ull - n1) << 32) - S0);
+            atomicAdd(p + 1, S0 + (n1 << 32) - S1);
+            if (n1) atomicAdd(p + 2, S1);          // only then is j0 + 1 a real left node
+        }
+    } else {
+        unsigned long long *p = Sl + (j + 1);
+        atomicAdd(p, (1ull << 32) - (unsigned long long)F);
+        atomicAdd(p + 1, (unsigned long long)F);
+    }
+}
+
 // Exact fixed-point charge deposit (Sec. 2.3 weights): with
 // U' = floor((x/dx - 1/2) 2^32) = j 2^32 + F, node j gets 2^32 - F and node
 // j+1 gets F.  Also accumulates the diagnostics sums w^2 and w.
@@ -125,9 +162,7 @@ __device__ __forceinline__ void deposit(T s, T w, unsigned long long *Sl, int ng
     const T jf = __builtin_floor(t);
     const uint32_t F = frac32(t - jf);
     const int j = min(max((int)jf, -1), ng - 1);
-    unsigned long long *p = Sl + (j + 1);
-    atomicAdd(p, (1ull << 32) - (unsigned long long)F);
-    atomicAdd(p + 1, (unsigned long long)F);
+    deposit_pair(j, F, Sl);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -356,20 +391,25 @@ __device__ __forceinline__ void run_one(T *U, T *W, int64_t q, const T *Et, unsi
     }
 }
 
-// All tiles [tb, te) of run R: wavefront k of the block takes tiles
-// tb + k, tb + k + nwaves, ...  Each lane handles UNROLL vectors of VEC
-// particles per iteration, all loads issued before any compute.  A lane's
-// particles are accumulated in index order for every UNROLL, so the tile
-// partial sums do not depend on it.
+// All tiles [tb, te) of run R.  Tile t of a run owns the block units
+// (kUnit particles each) t, t + ntiles, t + 2 ntiles, ...: the wavefronts of
+// the device, each on its own tile, sweep neighbouring units together.
+// Wavefronts take tiles one at a time from an LDS counter, so they finish a
+// chunk together whatever the tile count.  Each lane handles UNROLL vectors
+// of VEC particles per iteration, all loads issued before any compute; a
+// lane's particles are accumulated in index order for every UNROLL, so the
+// tile partial sums depend only on the run.
 template <typename T, int BLOCK, int UNROLL, bool PUSH>
 __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_table,
-                              unsigned long long *Sl, T *Et) {
+                              unsigned long long *Sl, T *Et, int *next_tile) {
     using V = typename Vec<T>::type;
     constexpr int VEC = Vec<T>::n;
     constexpr int PER = 64 * VEC * UNROLL;
+    constexpr int SPB = kUnit / PER;                 // sub-blocks per block unit
+    static_assert(kUnit % PER == 0, "a block unit holds whole sub-blocks");
     const int ng = R->ng;
     const int64_t np = R->np;
-    const int tile = R->tile;
+    const int ntiles = R->ntiles;
     T *U = (T *)R->u;
     T *W = (T *)R->w;
     double *part = R->tile_part;
@@ -383,52 +423,61 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
             Et[ng + 1] = tab[0];
         }
     }
+    if (threadIdx.x == 0) *next_tile = tb;
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     uint32_t flags = 0;
-    for (int t = __builtin_amdgcn_readfirstlane(tb + wave); t < te; t += BLOCK / 64) {
-        const int64_t p0 = (int64_t)t * tile;
-        const int64_t p1 = min(p0 + (int64_t)tile, np);
+    const int64_t nfull = np / kUnit;                // full block units of the run
+    const bool ragged = nfull * (int64_t)kUnit < np;
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(next_tile, 1);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= te) break;
         double a1 = 0.0, a2 = 0.0;
-        // Full blocks of PER particles, software-pipelined over two register
-        // sets: the loads of the next block are issued before the current
-        // block is processed and stored, so a wave waits for one load latency
-        // per block and never for its own stores.
-        const int64_t nb = (p1 - p0) / PER;
-        const int64_t last = p0 + (nb - 1) * PER;    // base of the last full block
+        // Full units of the tile in sub-blocks of PER particles,
+        // software-pipelined over two register sets: the loads of the next
+        // sub-block are issued before the current one is processed and
+        // stored, so a wave waits for one load latency per sub-block and
+        // never for its own stores.  Pairs of sub-blocks with unconditional
+        // loads (the load after the last pair re-reads the last sub-block,
+        // in bounds), so every iteration issues the same memory operations.
+        const int64_t nunits = t < nfull ? (nfull - 1 - t) / ntiles + 1 : 0;
+        const int64_t nb = nunits * SPB;
+        auto sub = [&](int64_t q) -> int64_t {
+            return ((int64_t)t + (q / SPB) * ntiles) * kUnit + (q % SPB) * PER;
+        };
         V au[UNROLL], aw[UNROLL], bu[UNROLL], bw[UNROLL];
-        if (nb > 0) load_block<V, VEC, UNROLL>(U, W, p0, lane, au, aw);
-        // Pairs of blocks with unconditional loads (the load after the last
-        // pair re-reads the last block, in bounds), so every iteration issues
-        // the same memory operations and a wave waits only for the loads it
-        // issued one block earlier.
+        if (nb > 0) load_block<V, VEC, UNROLL>(U, W, sub(0), lane, au, aw);
         const int64_t npairs = nb / 2;
         for (int64_t q = 0; q < npairs; ++q) {
-            const int64_t base = p0 + 2 * q * PER;
-            load_block<V, VEC, UNROLL>(U, W, base + PER, lane, bu, bw);
-            run_block<T, V, VEC, UNROLL, PUSH>(U, W, base, lane, au, aw, Et, Sl, ng, ngf, hi, a1, a2, flags);
-            load_block<V, VEC, UNROLL>(U, W, min(base + 2 * PER, last), lane, au, aw);
-            run_block<T, V, VEC, UNROLL, PUSH>(U, W, base + PER, lane, bu, bw, Et, Sl, ng, ngf, hi, a1, a2,
-                                               flags);
+            const int64_t b0 = sub(2 * q), b1 = sub(2 * q + 1), b2 = sub(min(2 * q + 2, nb - 1));
+            load_block<V, VEC, UNROLL>(U, W, b1, lane, bu, bw);
+            run_block<T, V, VEC, UNROLL, PUSH>(U, W, b0, lane, au, aw, Et, Sl, ng, ngf, hi, a1, a2, flags);
+            load_block<V, VEC, UNROLL>(U, W, b2, lane, au, aw);
+            run_block<T, V, VEC, UNROLL, PUSH>(U, W, b1, lane, bu, bw, Et, Sl, ng, ngf, hi, a1, a2, flags);
         }
-        if (nb & 1)                                  // au holds the last block
-            run_block<T, V, VEC, UNROLL, PUSH>(U, W, last, lane, au, aw, Et, Sl, ng, ngf, hi, a1, a2, flags);
-        // Ragged end of the tile (only a run's last tile): same per-lane
-        // order as a full block; whole vectors where they fit, then single
-        // particles.
-        for (int64_t base = p0 + nb * PER; base < p1; base += PER) {
-            for (int k = 0; k < UNROLL; ++k) {
-                const int64_t i = base + (int64_t)(k * 64 + lane) * VEC;
-                if (i + VEC <= p1) {
-                    V vu[1], vw[1];
-                    vu[0] = load_stream<V>(U + i);
-                    vw[0] = load_stream<V>(W + i);
-                    run_block<T, V, VEC, 1, PUSH>(U, W, i - (int64_t)lane * VEC, lane, vu, vw, Et, Sl, ng,
-                                                  ngf, hi, a1, a2, flags);
-                } else {
-                    for (int e = 0; e < VEC; ++e) {
-                        const int64_t q = i + e;
-                        if (q < p1) run_one<T, PUSH>(U, W, q, Et, Sl, ng, ngf, hi, a1, a2, flags);
+        if (nb & 1)
+            run_block<T, V, VEC, UNROLL, PUSH>(U, W, sub(nb - 1), lane, au, aw, Et, Sl, ng, ngf, hi, a1, a2,
+                                               flags);
+        // The run's partial last unit belongs to tile nfull mod ntiles: same
+        // per-lane order as a full unit; whole vectors where they fit, then
+        // single particles.
+        if (ragged && nfull % ntiles == t) {
+            for (int64_t base = nfull * kUnit; base < np; base += PER) {
+                for (int k = 0; k < UNROLL; ++k) {
+                    const int64_t i = base + (int64_t)(k * 64 + lane) * VEC;
+                    if (i + VEC <= np) {
+                        V vu[1], vw[1];
+                        vu[0] = load_stream<V>(U + i);
+                        vw[0] = load_stream<V>(W + i);
+                        run_block<T, V, VEC, 1, PUSH>(U, W, i - (int64_t)lane * VEC, lane, vu, vw, Et, Sl, ng,
+                                                      ngf, hi, a1, a2, flags);
+                    } else {
+                        for (int e = 0; e < VEC; ++e) {
+                            const int64_t q = i + e;
+                            if (q < np) run_one<T, PUSH>(U, W, q, Et, Sl, ng, ngf, hi, a1, a2, flags);
+                        }
                     }
                 }
             }
@@ -468,21 +517,33 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
     __syncthreads();
 }
 
+// Particle pass.  Single run (items == nullptr): workgroup b takes an
+// even share of the run's tiles.  Batch: workgroups take work items (chunks
+// of some run's tiles, largest first) from the shared queue until it is
+// empty; the last workgroup to find it empty resets the queue for the next
+// launch.  Any workgroup may take any chunk: nothing a chunk computes
+// depends on who computes it (per-tile partials, integer grid sums).
 template <typename T, int BLOCK, int UNROLL, bool PUSH>
-__global__ __launch_bounds__(BLOCK, (UNROLL >= 4 ? 4 : 6)) void step_kernel(
-    RunDev *runs, const WorkItem *items, const int32_t *wg_begin, int ng_lds) {
+__global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkItem *items, WorkQueue *queue,
+                                                    int ng_lds) {
     extern __shared__ unsigned long long lds[];
+    __shared__ uint32_t s_item;
+    __shared__ int s_tile;
     unsigned long long *Sl = lds;
     T *Et = reinterpret_cast<T *>(lds + ng_lds + 2);
     for (int g = threadIdx.x; g < ng_lds + 2; g += BLOCK) Sl[g] = 0ull;
-    int ib = 0, ie = 1;
-    if (items) {
-        ib = wg_begin[blockIdx.x];
-        ie = wg_begin[blockIdx.x + 1];
-    }
+    const uint32_t nitems = items ? queue->nitems : 1u;
     int prev_run = -1;
-    for (int it = ib; it < ie; ++it) {
-        int r, tb, te, chunk;
+    for (uint32_t round = 0;; ++round) {
+        uint32_t it = round;                          // single run: one chunk per workgroup
+        if (items) {
+            if (threadIdx.x == 0) s_item = atomicAdd(&queue->next, 1u);
+            __syncthreads();
+            it = s_item;
+            __syncthreads();                          // s_item is rewritten next round
+        }
+        if (it >= nitems) break;
+        int r = 0, tb, te, chunk;
         if (items) {
             const WorkItem wi = items[it];
             r = wi.run;
@@ -490,7 +551,6 @@ __global__ __launch_bounds__(BLOCK, (UNROLL >= 4 ? 4 : 6)) void step_kernel(
             te = wi.tile_end;
             chunk = wi.chunk;
         } else {
-            r = 0;
             const int64_t nt = runs[0].ntiles;
             tb = (int)(nt * blockIdx.x / gridDim.x);
             te = (int)(nt * (blockIdx.x + 1) / gridDim.x);
@@ -498,9 +558,17 @@ __global__ __launch_bounds__(BLOCK, (UNROLL >= 4 ? 4 : 6)) void step_kernel(
         }
         RunDev *R = runs + r;
         // the prologue (initial deposit) runs whatever the step target, even 0
-        if (te <= tb || (PUSH && R->step >= R->step_target) || R->ng > ng_lds) continue;
-        process_chunk<T, BLOCK, UNROLL, PUSH>(R, tb, te, chunk, r != prev_run, Sl, Et);
-        prev_run = r;
+        if (te > tb && !(PUSH && R->step >= R->step_target) && R->ng <= ng_lds) {
+            process_chunk<T, BLOCK, UNROLL, PUSH>(R, tb, te, chunk, r != prev_run, Sl, Et, &s_tile);
+            prev_run = r;
+        }
+    }
+    if (!items) return;
+    // Every other workgroup's last take from the queue has returned before
+    // its `done` increment, so the last one can reset both counters.
+    if (threadIdx.x == 0 && atomicAdd(&queue->done, 1u) == gridDim.x - 1) {
+        atomicExch(&queue->next, 0u);
+        atomicExch(&queue->done, 0u);
     }
 }
 
@@ -569,24 +637,24 @@ hipError_t step_prepare(const LaunchShape &ls, int precision) {
     return hipSuccess;
 }
 
-hipError_t launch_particles(RunDev *runs, const WorkItem *items, const int32_t *wg_begin, int grid,
+hipError_t launch_particles(RunDev *runs, const WorkItem *items, WorkQueue *queue, int grid,
                             const LaunchShape &ls, int ng_lds, int precision, int prologue,
                             hipStream_t stream) {
-    if (grid <= 0 || ng_lds <= 0 || ng_lds > kMaxNg) return hipErrorInvalidValue;
+    if (grid <= 0 || ng_lds <= 0 || ng_lds > kMaxNg || (items && !queue)) return hipErrorInvalidValue;
     const void *fn = kernel_select(ls, precision, prologue == 0);
     if (!fn) return hipErrorInvalidValue;
-    void *args[] = {(void *)&runs, (void *)&items, (void *)&wg_begin, (void *)&ng_lds};
+    void *args[] = {(void *)&runs, (void *)&items, (void *)&queue, (void *)&ng_lds};
     return hipLaunchKernel(fn, dim3(grid), dim3(ls.block), args, step_lds_bytes(precision, ng_lds),
                            stream);
 }
 
-hipError_t launch_step(RunDev *runs, const WorkItem *items, const int32_t *wg_begin, int grid,
+hipError_t launch_step(RunDev *runs, const WorkItem *items, WorkQueue *queue, int grid,
                        const LaunchShape &ls, int ng_lds, int precision, int prologue, int nsolve,
                        hipStream_t stream, const StepEvents *ev) {
     if (nsolve <= 0) return hipErrorInvalidValue;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev->e0, stream)) != hipSuccess) return e;
-    e = launch_particles(runs, items, wg_begin, grid, ls, ng_lds, precision, prologue, stream);
+    e = launch_particles(runs, items, queue, grid, ls, ng_lds, precision, prologue, stream);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev->e1, stream)) != hipSuccess) return e;
     void *sargs[] = {(void *)&runs, (void *)&prologue};

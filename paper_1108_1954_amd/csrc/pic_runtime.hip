@@ -98,8 +98,8 @@ pic_status validate(const pic_params *p) {
     if (!(finite_pos(p->rho0) && p->rho0 > 0)) return fail(PIC_EINVAL, "rho0 must be finite and > 0");
     if (p->precision != PIC_FP32 && p->precision != PIC_FP64)
         return fail(PIC_EINVAL, "precision must be PIC_FP32 or PIC_FP64");
-    if (p->tile < 0 || p->tile % 256 != 0 || p->tile > (1 << 20))
-        return fail(PIC_EINVAL, "tile must be 0 or a multiple of 256 up to 2^20 (got %d)", p->tile);
+    if (p->tile < 0 || p->tile % kUnit != 0 || p->tile > (1 << 20))
+        return fail(PIC_EINVAL, "tile must be 0 or a multiple of %d up to 2^20 (got %d)", kUnit, p->tile);
     if (p->history_cap < 0) return fail(PIC_EINVAL, "history_cap must be >= 0");
     return PIC_OK;
 }
@@ -117,9 +117,10 @@ int default_tile(int64_t np) {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t u, w, S, S_last, Ehat, Ehat64, E64, part, hist, total;
+    size_t u, w, u_alt, w_alt, sort, S, S_last, Ehat, Ehat64, E64, part, hist, total;
     int tile, ntiles;
     size_t esize;
+    bool sorting;         // alternate particle arrays and sort scratch present
 };
 
 Layout make_layout(const pic_params *p) {
@@ -136,6 +137,12 @@ Layout make_layout(const pic_params *p) {
     };
     L.u = take(np_pad * L.esize);
     L.w = take(np_pad * L.esize);
+    L.sorting = p->sort_every > 0;
+    if (L.sorting) {
+        L.u_alt = take(np_pad * L.esize);
+        L.w_alt = take(np_pad * L.esize);
+        L.sort = take(sort_scratch_bytes(p->np, p->ng));
+    }
     L.S = take((size_t)p->ng * 8);
     L.S_last = take((size_t)p->ng * 8);
     L.Ehat = take((size_t)p->ng * 4);
@@ -170,8 +177,16 @@ struct pic_run {
     LaunchShape shape;
     int grid = 1;
     double Q = 0, m = 0, dx = 0;
+    // Steps enqueued so far, and whether the particle arrays have traded
+    // places with their alternates (an odd number of cell sorts enqueued).
+    int64_t issued = 0;
+    bool swapped = false;
+    void *cur_u() const { return swapped ? host.u_alt : host.u; }
+    void *cur_w() const { return swapped ? host.w_alt : host.w; }
+    int sort_every() const { return lay.sorting ? p.sort_every : 0; }
     // graph replay cache
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr;       // graph_steps steps
+    hipGraphExec_t graph_sort = nullptr;  // cell sort + graph_steps steps
     int graph_steps = 0;
 };
 
@@ -229,7 +244,8 @@ void carve(pic_run *r) {
     RunDev &h = r->host;
     h.u = b + L.u;
     h.w = b + L.w;
-    h.u_alt = h.w_alt = nullptr;
+    h.u_alt = L.sorting ? b + L.u_alt : nullptr;
+    h.w_alt = L.sorting ? b + L.w_alt : nullptr;
     h.S = (unsigned long long *)(b + L.S);
     h.S_last = (unsigned long long *)(b + L.S_last);
     h.Ehat = (float *)(b + L.Ehat);
@@ -237,7 +253,8 @@ void carve(pic_run *r) {
     h.E64 = (double *)(b + L.E64);
     h.tile_part = (double *)(b + L.part);
     h.hist = (double *)(b + L.hist);
-    h.sort_hist = nullptr;
+    h.sort_scratch = L.sorting ? b + L.sort : nullptr;
+    h.sort_swap = 0;
 }
 
 // Convert host FP64 particles to engine units: the stored position is
@@ -309,7 +326,7 @@ pic_status init_device_state(pic_run *r) {
 // real particle passes on the run's own state and then puts it back).
 pic_status save_particles(const pic_run *r, char *dst, bool restore) {
     const size_t bytes = (size_t)r->p.np * r->lay.esize;
-    char *u = (char *)r->host.u, *w = (char *)r->host.w;
+    char *u = (char *)r->cur_u(), *w = (char *)r->cur_w();
     if (restore) {
         HIP_TRY(hipMemcpyAsync(u, dst, bytes, hipMemcpyDeviceToDevice, r->stream));
         HIP_TRY(hipMemcpyAsync(w, dst + bytes, bytes, hipMemcpyDeviceToDevice, r->stream));
@@ -454,6 +471,11 @@ extern "C" pic_status pic_create(const pic_params *params, const double *x0, con
     }
     r->dev = (RunDev *)(r->base + r->lay.total);
     DeviceInfo d = device_info();
+    if (r->lay.sorting && sort_prepare() != hipSuccess) {
+        if (r->owns_mem) (void)hipFree(r->base);
+        delete r;
+        return fail(PIC_EDEVICE, "cell-sort kernel setup failed");
+    }
     r->shape = d.shape;
     fill_constants(r);
     carve(r);
@@ -472,20 +494,56 @@ extern "C" pic_status pic_create(const pic_params *params, const double *x0, con
     return PIC_OK;
 }
 
+namespace {
+
+// True when the cell sort is due before the next step: every sort_every
+// steps, counted from creation (never before the first step).
+bool sort_due(const pic_run *r) {
+    const int k = r->sort_every();
+    return k > 0 && r->issued > 0 && r->issued % k == 0;
+}
+
+// Enqueue the next step of a single run (preceded by the cell sort when due).
+pic_status enqueue_step(pic_run *r, const StepEvents *ev = nullptr) {
+    hipError_t e = hipSuccess;
+    if (sort_due(r)) {
+        e = launch_sort(r->dev, r->p.np, r->p.ng, r->p.precision, r->host.sort_scratch, r->stream);
+        if (e == hipSuccess) r->swapped = !r->swapped;
+    }
+    if (e == hipSuccess)
+        e = launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng, r->p.precision, 0, 1,
+                        r->stream, ev);
+    if (e != hipSuccess) {
+        r->error = true;
+        return fail(PIC_EDEVICE, "step launch failed: %s", hipGetErrorString(e));
+    }
+    ++r->issued;
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" pic_status pic_sort(pic_run *r) {
+    pic_status st = check_run(r);
+    if (st != PIC_OK) return st;
+    if (r->batch_member) return fail(PIC_ESTATE, "batch members are sorted by the batch");
+    if (!r->lay.sorting) return fail(PIC_ESTATE, "run was created without cell sorting (sort_every <= 0)");
+    hipError_t e = launch_sort(r->dev, r->p.np, r->p.ng, r->p.precision, r->host.sort_scratch, r->stream);
+    if (e != hipSuccess) {
+        r->error = true;
+        return fail(PIC_EDEVICE, "sort launch failed: %s", hipGetErrorString(e));
+    }
+    r->swapped = !r->swapped;
+    return PIC_OK;
+}
+
 extern "C" pic_status pic_step(pic_run *r, int64_t nsteps) {
     pic_status st = check_run(r);
     if (st != PIC_OK) return st;
     if (r->batch_member) return fail(PIC_ESTATE, "batch members are stepped with pic_batch_step");
     if (nsteps < 0) return fail(PIC_EINVAL, "nsteps must be >= 0");
-    for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng,
-                                   r->p.precision, 0, 1, r->stream);
-        if (e != hipSuccess) {
-            r->error = true;
-            return fail(PIC_EDEVICE, "step launch failed: %s", hipGetErrorString(e));
-        }
-    }
-    return PIC_OK;
+    for (int64_t s = 0; s < nsteps && st == PIC_OK; ++s) st = enqueue_step(r);
+    return st;
 }
 
 extern "C" pic_status pic_step_graph(pic_run *r, int64_t nsteps, int32_t graph_steps) {
@@ -494,27 +552,50 @@ extern "C" pic_status pic_step_graph(pic_run *r, int64_t nsteps, int32_t graph_s
     if (r->batch_member) return fail(PIC_ESTATE, "batch members are stepped with pic_batch_step");
     if (nsteps < 0 || graph_steps < 1 || graph_steps > 4096)
         return fail(PIC_EINVAL, "need nsteps >= 0 and graph_steps in [1, 4096]");
-    if (r->graph && r->graph_steps != graph_steps) {
-        (void)hipGraphExecDestroy(r->graph);
-        r->graph = nullptr;
+    const int G = graph_steps, K = r->sort_every();
+    if (r->graph_steps != G) {
+        if (r->graph) (void)hipGraphExecDestroy(r->graph);
+        if (r->graph_sort) (void)hipGraphExecDestroy(r->graph_sort);
+        r->graph = r->graph_sort = nullptr;
+        r->graph_steps = G;
     }
-    if (!r->graph && nsteps >= graph_steps) {
-        const pic_run *rc = r;
-        pic_status gs = capture_graph(
-            [rc](hipStream_t s) {
-                return launch_step(rc->dev, nullptr, nullptr, rc->grid, rc->shape, rc->p.ng,
-                                   rc->p.precision, 0, 1, s);
-            },
-            graph_steps, &r->graph);
-        if (gs != PIC_OK) return gs;
-        r->graph_steps = graph_steps;
-    }
+    // Two graphs: G steps, and (with the cell sort) a sort followed by G
+    // steps.  A graph is replayed only where no sort falls inside it.
+    const pic_run *rc = r;
+    auto step_launch = [rc](hipStream_t s) {
+        return launch_step(rc->dev, nullptr, nullptr, rc->grid, rc->shape, rc->p.ng, rc->p.precision, 0, 1, s);
+    };
     int64_t left = nsteps;
-    while (r->graph && left >= graph_steps) {
-        HIP_TRY(hipGraphLaunch(r->graph, r->stream));
-        left -= graph_steps;
+    while (left > 0) {
+        const bool due = sort_due(r);
+        // steps until the next sort after this point
+        const int64_t room = K > 0 ? K - (due ? 0 : r->issued % K) : INT64_MAX;
+        if (left >= G && (due ? K >= G : room >= G)) {
+            hipGraphExec_t *gx = due ? &r->graph_sort : &r->graph;
+            if (!*gx) {
+                int first = 1;
+                st = capture_graph(
+                    [&](hipStream_t s) {
+                        hipError_t e = hipSuccess;
+                        if (due && first)
+                            e = launch_sort(rc->dev, rc->p.np, rc->p.ng, rc->p.precision, rc->host.sort_scratch, s);
+                        first = 0;
+                        return e == hipSuccess ? step_launch(s) : e;
+                    },
+                    G, gx);
+                if (st != PIC_OK) return st;
+            }
+            HIP_TRY(hipGraphLaunch(*gx, r->stream));
+            if (due) r->swapped = !r->swapped;
+            r->issued += G;
+            left -= G;
+        } else {
+            st = enqueue_step(r);
+            if (st != PIC_OK) return st;
+            --left;
+        }
     }
-    return pic_step(r, left);
+    return PIC_OK;
 }
 
 namespace {
@@ -561,11 +642,7 @@ extern "C" pic_status pic_step_profiled(pic_run *r, int64_t nsteps, double *ms_p
     if (r->batch_member) return fail(PIC_ESTATE, "batch members are stepped with pic_batch_step");
     if (nsteps < 1) return fail(PIC_EINVAL, "nsteps must be >= 1");
     st = profiled_steps(
-        [r](const StepEvents *ev) {
-            hipError_t e = launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng,
-                                       r->p.precision, 0, 1, r->stream, ev);
-            return e == hipSuccess ? PIC_OK : fail(PIC_EDEVICE, "step launch: %s", hipGetErrorString(e));
-        },
+        [r](const StepEvents *ev) { return enqueue_step(r, ev); },
         r->stream, nsteps, ms_particle, ms_solve);
     if (st == PIC_EDEVICE) r->error = true;
     return st;
@@ -610,7 +687,7 @@ extern "C" pic_status pic_read_raw(pic_run *r, void *u, void *w, int64_t cap) {
     const size_t n = (size_t)r->p.np;
     const size_t bytes = n * r->lay.esize;
     if (u) {
-        HIP_TRY(dev_read(r, u, r->host.u, bytes));
+        HIP_TRY(dev_read(r, u, r->cur_u(), bytes));
         // stored s = u + 1/2 with s >= 1/2: s - 1/2 is exact in either precision
         if (r->p.precision == PIC_FP32) {
             float *f = (float *)u;
@@ -620,7 +697,7 @@ extern "C" pic_status pic_read_raw(pic_run *r, void *u, void *w, int64_t cap) {
             for (size_t i = 0; i < n; ++i) d[i] -= 0.5;
         }
     }
-    if (w) HIP_TRY(dev_read(r, w, r->host.w, bytes));
+    if (w) HIP_TRY(dev_read(r, w, r->cur_w(), bytes));
     return PIC_OK;
 }
 
@@ -686,6 +763,7 @@ extern "C" pic_status pic_destroy(pic_run *r) {
     if (r->batch_member) return fail(PIC_ESTATE, "batch members are released with pic_batch_release");
     hipError_t e = hipStreamSynchronize(r->stream);
     if (r->graph) (void)hipGraphExecDestroy(r->graph);
+    if (r->graph_sort) (void)hipGraphExecDestroy(r->graph_sort);
     if (r->owns_mem) (void)hipFree(r->base);
     delete r;
     if (e != hipSuccess) return fail(PIC_EDEVICE, "device error at destroy: %s", hipGetErrorString(e));
@@ -753,6 +831,7 @@ struct Member {
     int64_t nsteps;        // steps requested
     int64_t launch_done;   // batch launch index after which the run is complete
     int64_t admit_seq = 0; // completion mark recorded after its prologue
+    int64_t admit_launch = 0;  // batch launches issued before it joined
     bool reported = false;
 };
 
@@ -779,9 +858,9 @@ struct pic_batch {
     Arena arena;
     RunDev *table = nullptr;          // device run table [max_runs]
     WorkItem *items_dev = nullptr;    // device work list
-    int32_t *wg_dev = nullptr;        // device per-workgroup offsets [grid + 1]
+    WorkQueue *queue_dev = nullptr;   // device work queue of the particle pass
     WorkItem *items_host = nullptr;   // pinned staging
-    int32_t *wg_host = nullptr;
+    WorkQueue *queue_host = nullptr;
     hipEvent_t staged = nullptr;      // staging buffers free again
     int item_cap = 0;
     int grid = 0, grid_max = 0, cus = 256;
@@ -817,9 +896,10 @@ pic_status batch_check(pic_batch *b) {
     return PIC_OK;
 }
 
-// Longest-processing-time assignment of chunks to the persistent workgroups.
-// Each run is split into chunks of about `target` particles (whole tiles);
-// chunks go, largest first, to the least-loaded workgroup.
+// Work list of the batched particle pass: each unfinished run is split into
+// chunks of about `target` particles (whole tiles), listed largest first;
+// the persistent workgroups take them in that order from the device queue,
+// which balances the load as it goes (longest-processing-time first).
 pic_status rebuild_schedule(pic_batch *b) {
     struct Chunk {
         int slot, tb, te, index, count;
@@ -840,39 +920,28 @@ pic_status rebuild_schedule(pic_batch *b) {
         const int per = (int)std::max<int64_t>(1, (target + tile - 1) / tile);
         const int count = (nt + per - 1) / per;
         for (int c = 0, t0 = 0; t0 < nt; ++c, t0 += per) {
-            int t1 = std::min(nt, t0 + per);
-            int64_t w = std::min<int64_t>((int64_t)t1 * tile, m.run->p.np) - (int64_t)t0 * tile;
+            const int t1 = std::min(nt, t0 + per);
+            // particles of tiles [t0, t1): whole tiles except the run's last
+            const int64_t w = std::min<int64_t>((int64_t)t1 * tile, m.run->p.np) - (int64_t)t0 * tile;
             chunks.push_back({m.slot, t0, t1, c, count, w + 4 * m.run->p.ng});
         }
     }
+    if ((int)chunks.size() > b->item_cap)
+        return fail(PIC_ENOMEM, "work list of %zu chunks exceeds capacity %d", chunks.size(), b->item_cap);
     std::sort(chunks.begin(), chunks.end(), [](const Chunk &a, const Chunk &c) {
         if (a.work != c.work) return a.work > c.work;
         if (a.slot != c.slot) return a.slot < c.slot;
         return a.tb < c.tb;
     });
-    std::vector<std::vector<WorkItem>> per_wg((size_t)b->grid);
-    std::vector<int64_t> load((size_t)b->grid, 0);
-    for (const Chunk &c : chunks) {
-        size_t k = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[k] += c.work;
-        per_wg[k].push_back({c.slot, c.tb, c.te, c.index, c.count, 0});
-    }
-    if ((int)chunks.size() > b->item_cap)
-        return fail(PIC_ENOMEM, "work list of %zu chunks exceeds capacity %d", chunks.size(), b->item_cap);
     HIP_TRY(hipEventSynchronize(b->staged));
-    int n = 0;
-    for (int k = 0; k < b->grid; ++k) {
-        b->wg_host[k] = n;
-        // consecutive chunks of one run stay together so the gather table is reused
-        std::sort(per_wg[(size_t)k].begin(), per_wg[(size_t)k].end(),
-                  [](const WorkItem &a, const WorkItem &c) {
-                      return a.run != c.run ? a.run < c.run : a.tile_begin < c.tile_begin;
-                  });
-        for (const WorkItem &w : per_wg[(size_t)k]) b->items_host[n++] = w;
+    const int n = (int)chunks.size();
+    for (int k = 0; k < n; ++k) {
+        const Chunk &c = chunks[(size_t)k];
+        b->items_host[k] = {c.slot, c.tb, c.te, c.index, c.count, 0};
     }
-    b->wg_host[b->grid] = n;
-    HIP_TRY(hipMemcpyAsync(b->wg_dev, b->wg_host, sizeof(int32_t) * (size_t)(b->grid + 1),
-                           hipMemcpyHostToDevice, b->stream));
+    // The previous launch left next = done = 0; this copy is ordered after it.
+    *b->queue_host = WorkQueue{0u, 0u, (uint32_t)n, 0u};
+    HIP_TRY(hipMemcpyAsync(b->queue_dev, b->queue_host, sizeof(WorkQueue), hipMemcpyHostToDevice, b->stream));
     if (n) HIP_TRY(hipMemcpyAsync(b->items_dev, b->items_host, sizeof(WorkItem) * (size_t)n,
                                   hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipEventRecord(b->staged, b->stream));
@@ -887,12 +956,50 @@ int64_t next_completion(const pic_batch *b) {
     return best;
 }
 
+// Cell sorts of batch members: a member that sorts every K steps is sorted
+// before its steps K+1, 2K+1, ... (counted from its admission), i.e. before
+// the batch launch that follows launch admit_launch + nK.
+bool member_sort_due(const Member &m, int64_t launches) {
+    const int k = m.run->sort_every();
+    const int64_t n = launches - m.admit_launch;
+    return k > 0 && n > 0 && n % k == 0 && launches < m.launch_done;
+}
+
+// Batch launch count of the next sort point after `launches` (INT64_MAX if none).
+int64_t next_sort_point(const pic_batch *b) {
+    int64_t best = INT64_MAX;
+    for (auto &kv : b->members) {
+        const Member &m = kv.second;
+        const int k = m.run->sort_every();
+        if (k <= 0 || m.launch_done <= b->launches) continue;
+        const int64_t n = b->launches - m.admit_launch;
+        const int64_t at = m.admit_launch + (n / k + 1) * k;
+        if (at < m.launch_done) best = std::min(best, at);
+    }
+    return best;
+}
+
+pic_status enqueue_member_sorts(pic_batch *b) {
+    for (auto &kv : b->members) {
+        Member &m = kv.second;
+        if (!member_sort_due(m, b->launches)) continue;
+        pic_run *r = m.run;
+        hipError_t e = launch_sort(r->dev, r->p.np, r->p.ng, PIC_FP32, r->host.sort_scratch, b->stream);
+        if (e != hipSuccess) {
+            b->error = true;
+            return fail(PIC_EDEVICE, "cell sort launch failed: %s", hipGetErrorString(e));
+        }
+        r->swapped = !r->swapped;
+    }
+    return PIC_OK;
+}
+
 pic_status ensure_graph(pic_batch *b) {
     if (b->graph || b->cfg.graph_steps <= 1) return PIC_OK;
     const pic_batch *bc = b;
     return capture_graph(
         [bc](hipStream_t s) {
-            return launch_step(bc->table, bc->items_dev, bc->wg_dev, bc->grid, bc->shape,
+            return launch_step(bc->table, bc->items_dev, bc->queue_dev, bc->grid, bc->shape,
                                bc->cfg.ng_max, PIC_FP32, 0, bc->cfg.max_runs, s);
         },
         b->cfg.graph_steps, &b->graph);
@@ -988,6 +1095,7 @@ extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream
     b->autotune = d.autotune;
     b->cus = d.cus;
     hipError_t e = step_prepare(b->shape, PIC_FP32);
+    if (e == hipSuccess) e = sort_prepare();
     if (e != hipSuccess) {
         delete b;
         return fail(PIC_EDEVICE, "kernel setup: %s", hipGetErrorString(e));
@@ -1005,9 +1113,9 @@ extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream
     }
     ok = ok && hipMalloc((void **)&b->table, sizeof(RunDev) * (size_t)cfg->max_runs) == hipSuccess;
     ok = ok && hipMalloc((void **)&b->items_dev, sizeof(WorkItem) * (size_t)b->item_cap) == hipSuccess;
-    ok = ok && hipMalloc((void **)&b->wg_dev, sizeof(int32_t) * (size_t)(b->grid_max + 1)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->queue_dev, sizeof(WorkQueue)) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&b->items_host, sizeof(WorkItem) * (size_t)b->item_cap) == hipSuccess;
-    ok = ok && hipHostMalloc((void **)&b->wg_host, sizeof(int32_t) * (size_t)(b->grid_max + 1)) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&b->queue_host, sizeof(WorkQueue)) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&b->idle_host, sizeof(RunDev)) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&b->io_stream, hipStreamNonBlocking) == hipSuccess;
@@ -1124,6 +1232,7 @@ extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, co
     m.bytes = lay.total;
     m.nsteps = nsteps;
     m.launch_done = b->launches + nsteps;
+    m.admit_launch = b->launches;
     st = add_mark(b);
     if (st != PIC_OK) {
         b->error = true;
@@ -1176,7 +1285,7 @@ pic_status batch_choose_shape(pic_batch *b) {
                                  b->shape = s;
                                  b->grid = b->cus * step_occupancy(s, b->cfg.ng_max, PIC_FP32);
                                  if (rebuild_schedule(b) != PIC_OK) return hipErrorInvalidValue;
-                                 return launch_particles(b->table, b->items_dev, b->wg_dev, b->grid, s,
+                                 return launch_particles(b->table, b->items_dev, b->queue_dev, b->grid, s,
                                                          b->cfg.ng_max, PIC_FP32, 0, b->stream);
                              },
                              &shape);
@@ -1219,7 +1328,10 @@ pic_status batch_advance(pic_batch *b, int64_t nsteps, std::vector<StepEvents> *
             if (st == PIC_OK) st = rebuild_schedule(b);
             if (st != PIC_OK) return st;
         }
-        int64_t k = std::min(left, nc - b->launches);    // launches before membership changes
+        pic_status sst = enqueue_member_sorts(b);
+        if (sst != PIC_OK) return sst;
+        // launches before membership changes or the next cell sort
+        int64_t k = std::min({left, nc - b->launches, next_sort_point(b) - b->launches});
         const int G = b->cfg.graph_steps;
         if (!evs && G > 1 && k >= G) {
             pic_status st = ensure_graph(b);
@@ -1241,7 +1353,7 @@ pic_status batch_advance(pic_batch *b, int64_t nsteps, std::vector<StepEvents> *
                 evs->push_back(e);
                 ev = &evs->back();
             }
-            hipError_t le = launch_step(b->table, b->items_dev, b->wg_dev, b->grid, b->shape,
+            hipError_t le = launch_step(b->table, b->items_dev, b->queue_dev, b->grid, b->shape,
                                         b->cfg.ng_max, PIC_FP32, 0, b->cfg.max_runs, b->stream, ev);
             if (le != hipSuccess) {
                 b->error = true;
@@ -1374,9 +1486,9 @@ extern "C" pic_status pic_batch_destroy(pic_batch *b) {
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
     if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->items_host) (void)hipHostFree(b->items_host);
-    if (b->wg_host) (void)hipHostFree(b->wg_host);
+    if (b->queue_host) (void)hipHostFree(b->queue_host);
     if (b->items_dev) (void)hipFree(b->items_dev);
-    if (b->wg_dev) (void)hipFree(b->wg_dev);
+    if (b->queue_dev) (void)hipFree(b->queue_dev);
     if (b->table) (void)hipFree(b->table);
     if (b->owns_arena && b->arena_base) (void)hipFree(b->arena_base);
     delete b;

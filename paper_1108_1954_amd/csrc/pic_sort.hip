@@ -1,0 +1,297 @@
+// Periodic cell sort of a run's particles (gfx950).
+//
+// Reorders (s, w) by the cell of the particle's left node,
+// key = clamp(floor(s - 1), -1, ng - 1) + 1 in [0, ng], the same index the
+// gather and the deposit use, so that neighbouring lanes work on
+// neighbouring cells.  The sort is a stable counting sort, so the order it
+// produces depends only on the particles (never on timing), and every later
+// result stays deterministic:
+//   1. count:   segment s (seg particles) counts its keys in LDS and stores
+//               them key-major, table[key * nseg + s];
+//   2. scan:    one exclusive prefix sum over the whole table gives the
+//               first destination of (key, segment) in the sorted order;
+//   3. scatter: each wavefront of a segment's workgroup takes a contiguous
+//               quarter of the segment, recounts it, and places its
+//               particles in input order (lanes with equal keys are ranked
+//               by lane within a 64-particle group, groups in order);
+//   4. swap:    the descriptor's particle arrays and their alternates trade
+//               places, so captured launches pick up the sorted arrays.
+// The physics is unchanged: a step treats every particle independently and
+// the fixed-point deposit does not depend on order.
+#include <algorithm>
+
+#include "pic_internal.h"
+
+namespace pic1d {
+
+namespace {
+
+constexpr int kSortBlock = 256;                 // 4 wavefronts
+constexpr int kSortWaves = kSortBlock / 64;
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;                  // consecutive elements per thread
+constexpr int kScanTile = kScanBlock * kScanItems;
+constexpr int kTopBlock = 1024;
+constexpr int kKeyBits = 14;                    // keys <= kMaxNg = 2^13
+
+template <typename T>
+__device__ __forceinline__ int cell_key(T s, int ng) {
+    const int j = min(max((int)__builtin_floor(s - T(1)), -1), ng - 1);
+    return j + 1;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// Active lanes whose key equals this lane's key.
+__device__ __forceinline__ unsigned long long match_key(int key) {
+    const unsigned long long act = __ballot(1);
+    const int k0 = __builtin_amdgcn_readfirstlane(key);
+    const unsigned long long same = __ballot(key == k0);
+    if (same == act) return act;                // common after a sort: one key per group
+    unsigned long long peers = act;
+#pragma unroll
+    for (int b = 0; b < kKeyBits; ++b) {
+        const bool bit = (key >> b) & 1;
+        const unsigned long long m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+// h[key] += 1 for every active lane, one LDS atomic per distinct key when
+// the group shares the first lane's key.
+__device__ __forceinline__ void count_key(uint32_t *h, int key) {
+    const int k0 = __builtin_amdgcn_readfirstlane(key);
+    const unsigned long long same = __ballot(key == k0);
+    if (key == k0) {
+        if (lane_id() == __builtin_ctzll(same)) atomicAdd(h + k0, (uint32_t)__popcll(same));
+    } else {
+        atomicAdd(h + key, 1u);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSortBlock) void sort_count_kernel(const RunDev *R, int seg, int nseg,
+                                                                uint32_t *table) {
+    extern __shared__ uint32_t h[];             // [ng + 1]
+    const int ng = R->ng;
+    const int64_t np = R->np;
+    const T *u = (const T *)R->u;
+    for (int k = threadIdx.x; k <= ng; k += kSortBlock) h[k] = 0;
+    __syncthreads();
+    const int s = blockIdx.x;
+    const int64_t b0 = (int64_t)s * seg, b1 = min(np, b0 + seg);
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kSortBlock) count_key(h, cell_key(u[i], ng));
+    __syncthreads();
+    for (int k = threadIdx.x; k <= ng; k += kSortBlock) table[(size_t)k * nseg + s] = h[k];
+}
+
+// Exclusive scan of v over the 256 threads of a block, in thread order.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *red, uint32_t *total) {
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) red[wv] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int k = 0; k < kScanBlock / 64; ++k) {
+        if (k < wv) off += red[k];
+        tot += red[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_reduce_kernel(const uint32_t *a, int64_t n, uint32_t *bsum) {
+    __shared__ uint32_t red[kScanBlock / 64];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t k = b0 + (int64_t)i * kScanBlock + threadIdx.x;
+        if (k < n) v += a[k];
+    }
+    uint32_t tot;
+    (void)block_exclusive_scan(v, red, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the block sums in place (one workgroup).
+__global__ __launch_bounds__(kTopBlock) void scan_top_kernel(uint32_t *bsum, int nb) {
+    __shared__ uint32_t red[kTopBlock / 64];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += kTopBlock) {
+        const int k = base + threadIdx.x;
+        const uint32_t v = k < nb ? bsum[k] : 0u;
+        uint32_t inc = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) red[wv] = inc;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (int q = 0; q < kTopBlock / 64; ++q) {
+            if (q < wv) off += red[q];
+            tot += red[q];
+        }
+        __syncthreads();
+        if (k < nb) bsum[k] = carry + off + inc - v;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_down_kernel(uint32_t *a, int64_t n, const uint32_t *bsum) {
+    __shared__ uint32_t red[kScanBlock / 64];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = b0 + i < n ? a[b0 + i] : 0u;
+        sum += v[i];
+    }
+    uint32_t tot;
+    uint32_t run = bsum[blockIdx.x] + block_exclusive_scan(sum, red, &tot);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        if (b0 + i < n) a[b0 + i] = run;
+        run += v[i];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(RunDev *R, int seg, int nseg,
+                                                                  const uint32_t *offs) {
+    extern __shared__ uint32_t cw[];            // [kSortWaves][ng + 1]
+    const int ng = R->ng, nk = ng + 1;
+    const int64_t np = R->np;
+    const T *u = (const T *)R->u;
+    const T *w = (const T *)R->w;
+    T *uo = (T *)R->u_alt;
+    T *wo = (T *)R->w_alt;
+    const int s = blockIdx.x, wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t b0 = (int64_t)s * seg, b1 = min(np, b0 + seg);
+    const int64_t sub = (b1 - b0 + kSortBlock - 1) / kSortBlock * 64;    // per wavefront, multiple of 64
+    const int64_t w0 = min(b1, b0 + wave * sub), w1 = min(b1, w0 + sub);
+    uint32_t *mine = cw + wave * nk;
+    for (int k = threadIdx.x; k < kSortWaves * nk; k += kSortBlock) cw[k] = 0;
+    __syncthreads();
+    for (int64_t i = w0 + lane; i < w1; i += 64) count_key(mine, cell_key(u[i], ng));
+    __syncthreads();
+    // first destination of (key, wavefront): the segment's offset plus the
+    // counts of the earlier wavefronts
+    for (int k = threadIdx.x; k < nk; k += kSortBlock) {
+        uint32_t run = offs[(size_t)k * nseg + s];
+        for (int v = 0; v < kSortWaves; ++v) {
+            const uint32_t c = cw[v * nk + k];
+            cw[v * nk + k] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    uint32_t bad = 0;
+    for (int64_t g = w0; g < w1; g += 64) {
+        const int64_t i = g + lane;
+        if (i < w1) {
+            const T su = u[i], sw = w[i];
+            const int key = cell_key(su, ng);
+            const unsigned long long peers = match_key(key);
+            const int leader = __builtin_ctzll(peers);
+            const uint32_t rank = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+            uint32_t base = 0;
+            if (lane == leader) {
+                base = mine[key];
+                mine[key] = base + (uint32_t)__popcll(peers);
+            }
+            base = (uint32_t)__shfl((int)base, leader);
+            const uint32_t dst = base + rank;
+            if (dst < (uint64_t)np) {
+                uo[dst] = su;
+                wo[dst] = sw;
+            } else {
+                bad = 1;
+            }
+        }
+    }
+    if (bad) atomicOr(&R->flags, 4u);
+}
+
+__global__ void sort_swap_kernel(RunDev *R) {
+    if (threadIdx.x == 0) {
+        void *t = R->u;
+        R->u = R->u_alt;
+        R->u_alt = t;
+        t = R->w;
+        R->w = R->w_alt;
+        R->w_alt = t;
+        R->sort_swap ^= 1;
+    }
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+SortPlan sort_plan(int64_t np, int ng) {
+    SortPlan p{};
+    const int64_t per = (np + kMaxSortSegments - 1) / kMaxSortSegments;
+    p.seg = (int)std::max<int64_t>(4096, (per + 1023) / 1024 * 1024);
+    p.nseg = (int)((np + p.seg - 1) / p.seg);
+    p.table_len = (int64_t)(ng + 1) * p.nseg;
+    p.nblk = (int)((p.table_len + kScanTile - 1) / kScanTile);
+    return p;
+}
+
+size_t sort_scratch_bytes(int64_t np, int ng) {
+    const SortPlan p = sort_plan(np, ng);
+    return align256((size_t)p.table_len * 4) + align256((size_t)p.nblk * 4);
+}
+
+hipError_t sort_prepare() {
+    const size_t lds = (size_t)kSortWaves * (kMaxNg + 1) * sizeof(uint32_t);
+    hipError_t e = hipFuncSetAttribute((const void *)sort_scatter_kernel<float>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)sort_scatter_kernel<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_sort(RunDev *R, int64_t np, int ng, int precision, void *scratch, hipStream_t stream) {
+    if (np < 1 || ng < 2 || ng > kMaxNg || !scratch) return hipErrorInvalidValue;
+    const SortPlan p = sort_plan(np, ng);
+    uint32_t *table = (uint32_t *)scratch;
+    uint32_t *bsum = (uint32_t *)((char *)scratch + align256((size_t)p.table_len * 4));
+    const size_t lds_count = (size_t)(ng + 1) * sizeof(uint32_t);
+    const size_t lds_scatter = (size_t)kSortWaves * lds_count;
+    int seg = p.seg, nseg = p.nseg, nb = p.nblk;
+    int64_t n = p.table_len;
+    void *cargs[] = {(void *)&R, (void *)&seg, (void *)&nseg, (void *)&table};
+    const void *count = precision ? (const void *)sort_count_kernel<double> : (const void *)sort_count_kernel<float>;
+    hipError_t e = hipLaunchKernel(count, dim3(nseg), dim3(kSortBlock), cargs, lds_count, stream);
+    if (e != hipSuccess) return e;
+    void *rargs[] = {(void *)&table, (void *)&n, (void *)&bsum};
+    e = hipLaunchKernel((const void *)scan_reduce_kernel, dim3(nb), dim3(kScanBlock), rargs, 0, stream);
+    if (e != hipSuccess) return e;
+    void *targs[] = {(void *)&bsum, (void *)&nb};
+    e = hipLaunchKernel((const void *)scan_top_kernel, dim3(1), dim3(kTopBlock), targs, 0, stream);
+    if (e != hipSuccess) return e;
+    e = hipLaunchKernel((const void *)scan_down_kernel, dim3(nb), dim3(kScanBlock), rargs, 0, stream);
+    if (e != hipSuccess) return e;
+    const void *scatter =
+        precision ? (const void *)sort_scatter_kernel<double> : (const void *)sort_scatter_kernel<float>;
+    void *sargs[] = {(void *)&R, (void *)&seg, (void *)&nseg, (void *)&table};
+    e = hipLaunchKernel(scatter, dim3(nseg), dim3(kSortBlock), sargs, lds_scatter, stream);
+    if (e != hipSuccess) return e;
+    void *wargs[] = {(void *)&R};
+    return hipLaunchKernel((const void *)sort_swap_kernel, dim3(1), dim3(64), wargs, 0, stream);
+}
+
+}  // namespace pic1d

@@ -24,7 +24,7 @@ PIC_HIST_COLS = 4
 PIC_FLAG_NONFINITE, PIC_FLAG_MULTIWRAP = 1, 2
 
 SYMBOLS = (
-    "pic_last_error", "pic_version", "pic_footprint", "pic_create", "pic_step", "pic_step_graph",
+    "pic_last_error", "pic_version", "pic_footprint", "pic_create", "pic_sort", "pic_step", "pic_step_graph",
     "pic_step_profiled", "pic_batch_step_profiled", "pic_diagnostics", "pic_read_particles", "pic_read_raw", "pic_read_grid", "pic_read_history",
     "pic_destroy", "pic_batch_create", "pic_batch_admit", "pic_batch_step", "pic_batch_poll",
     "pic_batch_run", "pic_batch_release", "pic_batch_usage", "pic_batch_destroy",
@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "pic_footprint": [P, C.POINTER(sz)],
         "pic_create": [P, dptr, dptr, vp, sz, vp, C.POINTER(vp)],
+        "pic_sort": [vp],
         "pic_step": [vp, i64],
         "pic_step_graph": [vp, i64, i32],
         "pic_step_profiled": [vp, i64, dptr, dptr],
@@ -154,6 +155,10 @@ def pic_create(params: pic_params, x0, v_mhalf, dev_mem: Optional[int] = None, d
     _check(load().pic_create(C.byref(params), _dptr(x0), _dptr(v), dev_mem, dev_bytes, stream,
                              C.byref(out)))
     return out
+
+
+def pic_sort(run) -> None:
+    _check(load().pic_sort(run))
 
 
 def pic_step(run, nsteps: int) -> None:
@@ -307,6 +312,9 @@ class Run:
             pic_step_graph(self.handle, n, graph_steps)
         else:
             pic_step(self.handle, n)
+
+    def sort(self) -> None:
+        pic_sort(self.handle)
 
     def diagnostics(self, grids: bool = False):
         return pic_diagnostics(self.handle, self.params.ng if grids else 0)

@@ -53,7 +53,7 @@ def good(**kw):
 @pytest.mark.parametrize("bad", [
     dict(ng=1), dict(ng=P.PIC_MAX_NG + 1), dict(np=0), dict(np=1 << 31), dict(L=0.0),
     dict(L=float("nan")), dict(dt=0.0), dict(dt=-1.0), dict(qm=0.0), dict(rho0=0.0),
-    dict(precision=2), dict(tile=100), dict(tile=-256), dict(history_cap=-1),
+    dict(precision=2), dict(tile=100), dict(tile=-256), dict(tile=512), dict(history_cap=-1),
 ])
 def test_footprint_rejects_invalid_parameters(lib, bad):
     with pytest.raises(P.PicError) as e:

@@ -104,9 +104,10 @@ def test_initial_deposit_and_solve(precision):
     (P.PIC_FP32, 300_001, 512, 0),        # many tiles, ragged tail (np mod 4 = 1)
     (P.PIC_FP32, 70_003, 100, 1024),      # non power-of-two grid, explicit tile
     (P.PIC_FP64, 300_001, 512, 0),
-    (P.PIC_FP64, 70_003, 8192, 256),      # largest grid, FP64 state (128 KiB LDS)
+    (P.PIC_FP64, 70_003, 8192, 3072),     # largest grid, FP64 state (128 KiB LDS), 3-unit tiles
     (P.PIC_FP32, 1, 2, 0),                # one particle, smallest grid
     (P.PIC_FP32, 5, 3, 0),
+    (P.PIC_FP32, 5000, 16, 1024),         # ntiles > 1 with the ragged unit in tile 0
 ])
 def test_single_step_matches_oracle(precision, np_, ng, tile):
     """From the same (downloaded) state and field, one GPU step agrees with the

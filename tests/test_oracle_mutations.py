@@ -34,6 +34,9 @@ MUTANTS = [
     ("kinetic energy factor", "row[0] = 0.25 * m * (acc[0] + acc[1]);", "row[0] = 0.5 * m * (acc[0] + acc[1]);"),
     ("cg beta inverted", "double beta = rr_new / rr;", "double beta = rr / rr_new;"),
     ("cg pinned row", "r[g] = g == 0 ? 0.0 : -rho[g] * dx * dx;", "r[g] = -rho[g] * dx * dx;"),
+    ("cell key half-cell shift sign", "double j = floor(u - 0.5);", "double j = floor(u + 0.5);"),
+    ("cell order not stable", "for (int64_t i = 0; i < np; ++i)\n        perm[",
+     "for (int64_t i = np - 1; i >= 0; --i)\n        perm["),
 ]
 
 # The pins run against every build (argument lists for the parametrised ones).
@@ -41,6 +44,8 @@ PINS = [
     (T.test_plain_deposit_matches_triangle_bruteforce, [(2,), (4,), (8,)]),
     (T.test_fixed_deposit_total_is_exact_and_matches_bruteforce, [(3,), (8,)]),
     (T.test_fixed_deposit_hand_derived_golden_cases, [()]),
+    (T.test_cell_order_hand_derived_case, [()]),
+    (T.test_cell_order_is_a_stable_sort_by_nearest_node, [(5,), (64,)]),
     (T.test_fixed_density_matches_plain_density, [()]),
     (T.test_solve_matches_dense_linear_algebra, [(8,), (17,)]),
     (T.test_solve_single_mode_closed_form, [(16, 1), (64, 3)]),

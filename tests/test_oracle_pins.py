@@ -62,6 +62,31 @@ def test_fixed_deposit_total_is_exact_and_matches_bruteforce(ng):
     np.testing.assert_allclose(S / TWO32, W.sum(axis=0), rtol=0, atol=u.size * 2.0 ** -31)
 
 
+def test_cell_order_hand_derived_case():
+    # ng = 4: left stencil nodes floor(u - 1/2) = [3, -1, 1, 0, 3, 1]
+    u = [3.9, 0.2, 1.7, 0.6, 3.5, 1.5]
+    assert O.cell_order(4, u).tolist() == [1, 3, 2, 5, 0, 4]
+
+
+@pytest.mark.parametrize("ng", [2, 5, 64])
+def test_cell_order_is_a_stable_sort_by_nearest_node(ng):
+    """The left stencil node is one below the nearest node, so the order
+    equals a library stable sort by the nearest-node index floor(u + 1/2).
+    Positions are FP32 values (as the engine stores them) plus exact
+    half-integers and both ends of the domain."""
+    rng = np.random.default_rng(ng)
+    u = (rng.random(5000) * ng).astype(np.float32).astype(np.float64)
+    u[:ng] = np.arange(ng) + 0.5
+    u[ng] = 0.0
+    u[ng + 1] = np.nextafter(np.float32(ng), np.float32(0))
+    rng.shuffle(u)
+    perm = O.cell_order(ng, u)
+    assert sorted(perm.tolist()) == list(range(u.size))
+    np.testing.assert_array_equal(perm, np.argsort(np.floor(u + 0.5), kind="stable"))
+    # sorted by position at cell resolution
+    assert np.all(np.diff(np.floor(u[perm] + 0.5)) >= 0)
+
+
 def test_fixed_deposit_hand_derived_golden_cases():
     n = 0
     for line in open(os.path.join(GOLDEN, "deposit_fixed_cases.txt")):
