@@ -1333,9 +1333,13 @@ pic_status batch_advance(pic_batch *b, int64_t nsteps, std::vector<StepEvents> *
         // launches before membership changes or the next cell sort
         int64_t k = std::min({left, nc - b->launches, next_sort_point(b) - b->launches});
         const int G = b->cfg.graph_steps;
-        if (!evs && G > 1 && k >= G) {
+        if (!evs && G > 1) {
+            // captured on the first step call (also a short one), so later
+            // calls only replay
             pic_status st = ensure_graph(b);
             if (st != PIC_OK) return st;
+        }
+        if (!evs && G > 1 && k >= G) {
             while (k >= G) {
                 HIP_TRY(hipGraphLaunch(b->graph, b->stream));
                 b->launches += G;

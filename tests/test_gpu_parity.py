@@ -186,21 +186,29 @@ def test_graph_replay_is_bit_identical_to_plain_launches():
 
 # ----------------------------------------------------- runs vs the oracle ---
 
-def test_two_stream_history_against_fp64_oracle():
+@pytest.mark.parametrize("precision,lin_tol", [(P.PIC_FP32, 1e-3), (P.PIC_FP64, 1e-9)])
+def test_two_stream_history_against_fp64_oracle(precision, lin_tol):
     """Two-stream run (Ng=64, Np=10,000, 200 steps): W_E history of the
-    FP32/fixed-point engine vs the FP64 oracle from the same FP64 inputs."""
+    engine (FP32 or FP64 state, fixed-point deposit) vs the plain FP64
+    oracle from the same FP64 inputs.  FP32 state: positions round once to
+    2^-24 relative, which the linear instability carries along; FP64 state:
+    only FP64 rounding in another operation order, amplified by e^{gamma t}
+    (~30x by t = 10), plus the 2^-32 quantisation of the deposit weights."""
     spec = I.two_stream_small()
     x, v = spec.particles()
-    run, p = make_run(spec, history=spec.nsteps, x=x, v=v)
+    run, p = make_run(spec, precision=precision, history=spec.nsteps, x=x, v=v)
     with run:
         run.step(spec.nsteps)
         h = run.history()
-    ref = O.run(oracle_params(p), x, v, spec.nsteps, mode=O.DEPOSIT_FIXED)["hist"]
+    ref = O.run(oracle_params(p), x, v, spec.nsteps, mode=O.DEPOSIT_PLAIN)["hist"]
     we, we_o = h[:, 1], ref[:, 1]
     lin = slice(0, 100)                                   # linear phase, t < 10
     err_lin = np.abs(we[lin] - we_o[lin]).max() / we_o[lin].max()
-    assert err_lin < 1e-3, err_lin
-    # momentum conserved to FP32 rounding; energy as well as the oracle's
+    err_all = np.abs(we - we_o).max() / we_o.max()
+    print(f"two-stream W_E vs FP64 oracle, precision {precision}: linear phase {err_lin:.3e}, "
+          f"200 steps {err_all:.3e}", flush=True)
+    assert err_lin < lin_tol, err_lin
+    # momentum conserved to rounding; energy as well as the oracle's
     m = O.particle_mass(oracle_params(p))
     assert np.abs(h[:, 2] - h[0, 2]).max() < 1e-5 * m * np.abs(v).sum()
     et = h[:, 0] + h[:, 1]
