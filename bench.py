@@ -213,11 +213,56 @@ def main():
         ms2 = ev0.elapsed_time(ev1) / K
         mp2, msv2 = P.pic_step_profiled(r2.handle, prof_steps)
         r2.close()
+        # cell sort (a7) on the same run, which is created with room for it
+        p2s = P.make_params(s2.L, s2.ng, s2.np_, s2.dt, sort_every=1 << 30)
+        x, v = s2.particles()
+        r3 = P.Run(p2s, x, v)
+        del x, v
+        r3.step(2)
+
+        def timed_sort():
+            torch.cuda.synchronize()
+            ev0.record()
+            r3.sort()
+            ev1.record()
+            torch.cuda.synchronize()
+            return ev0.elapsed_time(ev1)
+        sort_random = timed_sort()                         # from the loaded (random) order
+        sort_sorted = min(timed_sort() for _ in range(3))  # already in cell order
+        mp_sorted, _ = P.pic_step_profiled(r3.handle, prof_steps)
+        r3.close()
         single = {"workload": "warm two-stream, np=2^26, ng=4096, L=131.39, dt=0.1",
                   "value": s2.np_ / (ms2 * 1e-3), "ms_per_step": ms2,
                   "particle_pass_ms": mp2, "solve_ms": msv2,
-                  "particle_pass_GBps": BYTES_PER_PSTEP * s2.np_ / (mp2 * 1e6)}
-        log(f"single run: {ms2:.3f} ms/step, particle pass {mp2:.3f} ms, solve {msv2:.3f} ms")
+                  "particle_pass_GBps": BYTES_PER_PSTEP * s2.np_ / (mp2 * 1e6),
+                  "cell_sort": {"ms_from_random_order": sort_random, "ms_when_sorted": sort_sorted,
+                                "particle_pass_ms_after_sort": mp_sorted,
+                                "note": "reported overhead; the engine sorts only when asked (sort_every > 0)"}}
+        log(f"single run: {ms2:.3f} ms/step, particle pass {mp2:.3f} ms, solve {msv2:.3f} ms; cell sort "
+            f"{sort_random:.3f} ms (random order), {sort_sorted:.3f} ms (sorted), pass after sort {mp_sorted:.3f} ms")
+
+    # ----------------------------- the paper's weak-scaling workload, one GPU
+    paper = None
+    if not args.no_single:
+        sp = I.paper_weak_scaling(cores=128)
+        paper = {"workload": f"the paper's weak-scaling run at its 128-thread size on one GPU: ng={sp.ng}, "
+                             f"np={sp.np_}, L={sp.L:.1f}, Maxwellian vth=0.2, dt=0.1, {sp.nsteps} cycles; "
+                             "particles drawn on the device (pic_create_loaded)"}
+        for label, solver in (("exact_solve", P.PIC_SOLVE_EXACT), ("paper_cg_150", P.PIC_SOLVE_CG_PAPER)):
+            pp = P.make_params(sp.L, sp.ng, sp.np_, sp.dt, solver=solver, cg_iters=150)
+            rp = P.Run(pp, loader=P.make_loader(**sp.loader))
+            rp.step(args.graph_steps, graph_steps=args.graph_steps)   # warm, incl. graph capture
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rp.step(sp.nsteps, graph_steps=args.graph_steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            mp, ms = P.pic_step_profiled(rp.handle, prof_steps)
+            rp.close()
+            paper[label] = {"seconds_per_1000_cycles": wall * 1000 / sp.nsteps,
+                            "ms_per_cycle": 1e3 * wall / sp.nsteps, "particle_pass_ms": mp, "solve_ms": ms,
+                            "particle_steps_per_s": sp.np_ * sp.nsteps / wall}
+        log(f"paper workload: {paper}")
 
     # ------------------------------------------------------------- serving
     serving = None
@@ -272,6 +317,7 @@ def main():
         "plain": plain,
         "batched_vs_plain": (batched_rate / plain["value"]) if plain else None,
         "single_run": single,
+        "paper_weak_scaling_one_gpu": paper,
         "serving": serving,
         "cpu_baseline": cpu,
     }

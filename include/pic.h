@@ -65,7 +65,8 @@ typedef enum { PIC_FP32 = 0, PIC_FP64 = 1 } pic_precision;
 
 /* Run parameters (Appendix A lists the paper's: L, ng, np, dt, qm, rho0).
  * Validation: ng in [2, PIC_MAX_NG]; 1 <= np < 2^31; L > 0; dt > 0;
- * qm != 0; rho0 > 0; all finite; precision PIC_FP32 or PIC_FP64. */
+ * qm != 0; rho0 > 0; all finite; precision PIC_FP32 or PIC_FP64;
+ * solver PIC_SOLVE_EXACT or PIC_SOLVE_CG_PAPER; 0 <= cg_iters <= 100000. */
 typedef struct pic_params {
     double  L;            /* periodic domain length                          */
     int32_t ng;           /* cells = grid nodes                              */
@@ -77,7 +78,20 @@ typedef struct pic_params {
     int32_t sort_every;   /* cell sort every K > 0 steps; <= 0 never (no room reserved) */
     int32_t tile;         /* particles per tile (multiple of 1024); 0 = default */
     int64_t history_cap;  /* per-step history rows kept on the device        */
+    int32_t solver;       /* PIC_SOLVE_EXACT (default) or PIC_SOLVE_CG_PAPER   */
+    int32_t cg_iters;     /* CG iterations for PIC_SOLVE_CG_PAPER; 0 = 150     */
 } pic_params;
+
+/* Field solvers of the periodic three-point system (Sec. 2.2).
+ * PIC_SOLVE_EXACT: exact solution with zero-mean potential (prefix sum of
+ *   the face field); equal to the converged CG.
+ * PIC_SOLVE_CG_PAPER: the paper's matrix-free conjugate gradient (Sec. 2.2,
+ *   Sec. 3.3): potential at node 0 held at zero, started from zero, a fixed
+ *   number of iterations (the paper uses 150), then the central difference.
+ *   It reproduces the paper's closing step including its non-convergence at
+ *   large ng (150 iterations do not converge for ng above ~150). */
+#define PIC_SOLVE_EXACT 0
+#define PIC_SOLVE_CG_PAPER 1
 
 #define PIC_MAX_NG 8192
 
@@ -125,6 +139,37 @@ pic_status pic_footprint(const pic_params *params, size_t *bytes);
  * dev_mem/dev_bytes: see Ownership above.  On success *out owns the run. */
 pic_status pic_create(const pic_params *params, const double *x0, const double *v_mhalf,
                       void *dev_mem, size_t dev_bytes, void *stream, pic_run **out);
+
+/* Device-side loader: the initial particles are drawn on the GPU instead of
+ * being uploaded.  Draw i of stream s is the SplitMix64 output (Steele, Lea
+ * and Flood, OOPSLA 2014) for the counter base(seed, s) + (i + 1) gamma,
+ * base(seed, s) = mix(seed * 0x100000001B3 + s * 0x9E37 + 1), gamma =
+ * 0x9E3779B97F4A7C15; uniforms u = (draw >> 11) 2^-53; normals
+ * n = sqrt(-2 log1p(-u)) cos(2 pi u') from draws i of streams vel_stream
+ * and vel_stream + 1.  Particle i:
+ *   x0 = L u_i (stream pos_stream),  x = x0 + amp sin(k x0) wrapped to [0, L),
+ *   v^{-1/2} = v0 (-1)^i if two_beams else v0, plus vth n_i,
+ * a uniform or single-mode-displaced plasma with drifting beams and a
+ * Maxwellian spread (the loads of Sec. 4 and the appendix).  A host can
+ * reproduce every value; device sin/log1p/cos may differ from a host
+ * library's in the last bit. */
+typedef struct pic_loader {
+    uint64_t seed;
+    int32_t  pos_stream;   /* stream of the position uniforms              */
+    int32_t  vel_stream;   /* first of the two streams of the normals      */
+    double   amp;          /* displacement amplitude (length)              */
+    double   k;            /* its wavenumber                               */
+    double   v0;           /* drift speed                                  */
+    double   vth;          /* thermal spread, >= 0                         */
+    int32_t  two_beams;    /* 1: drift +v0 for even i, -v0 for odd i       */
+    int32_t  pad_;
+} pic_loader;
+
+/* pic_create with the particles drawn on the device by `loader` (no host
+ * arrays, no upload).  EINVAL if (|v0| + 8.58 vth) dt >= L: the normals are
+ * bounded by sqrt(-2 ln 2^-53) < 8.58, so the single-wrap contract holds. */
+pic_status pic_create_loaded(const pic_params *params, const pic_loader *loader, void *dev_mem,
+                             size_t dev_bytes, void *stream, pic_run **out);
 
 /* Enqueue `nsteps` >= 0 steps (asynchronous; returns before they run).
  * With sort_every = K > 0, the particles are reordered by cell (pic_sort)
@@ -209,6 +254,10 @@ pic_status pic_batch_create(const pic_batch_config *cfg, void *stream, pic_batch
  * puts the batch in the error state (PIC_EDEVICE, then PIC_ESTATE). */
 pic_status pic_batch_admit(pic_batch *b, const pic_params *params, const double *x0,
                            const double *v_mhalf, int64_t nsteps, int64_t *run_id);
+
+/* pic_batch_admit with the particles drawn on the device by `loader`. */
+pic_status pic_batch_admit_loaded(pic_batch *b, const pic_params *params, const pic_loader *loader,
+                                  int64_t nsteps, int64_t *run_id);
 
 /* Advance every unfinished run by up to `nsteps` steps (asynchronous). */
 pic_status pic_batch_step(pic_batch *b, int64_t nsteps);

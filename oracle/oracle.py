@@ -23,9 +23,9 @@ DEPOSIT_FIXED = 1
 
 
 class Params(C.Structure):
-    _fields_ = [("L", C.c_double), ("ng", C.c_int32), ("pad_", C.c_int32),
+    _fields_ = [("L", C.c_double), ("ng", C.c_int32), ("solver", C.c_int32),
                 ("np", C.c_int64), ("dt", C.c_double), ("qm", C.c_double),
-                ("rho0", C.c_double)]
+                ("rho0", C.c_double), ("cg_iters", C.c_int32), ("pad_", C.c_int32)]
 
 
 def build(src: str = SRC, out: str = LIB) -> str:
@@ -86,8 +86,13 @@ def _bind(L):
     return L
 
 
-def params(L: float, ng: int, np: int, dt: float = 0.1, qm: float = -1.0, rho0: float = 1.0) -> Params:
-    return Params(L=float(L), ng=int(ng), pad_=0, np=int(np), dt=float(dt), qm=float(qm), rho0=float(rho0))
+SOLVE_EXACT, SOLVE_CG_PAPER = 0, 1
+
+
+def params(L: float, ng: int, np: int, dt: float = 0.1, qm: float = -1.0, rho0: float = 1.0,
+           solver: int = SOLVE_EXACT, cg_iters: int = 0) -> Params:
+    return Params(L=float(L), ng=int(ng), solver=int(solver), np=int(np), dt=float(dt), qm=float(qm),
+                  rho0=float(rho0), cg_iters=int(cg_iters), pad_=0)
 
 
 def _f64(a) -> np.ndarray:

@@ -56,11 +56,13 @@
 typedef struct {
     double  L;     /* periodic domain length                       */
     int32_t ng;    /* number of cells (= grid nodes)               */
-    int32_t pad_;
+    int32_t solver; /* field solve of whole steps: 0 exact, 1 the paper's CG */
     int64_t np;    /* number of computational particles            */
     double  dt;    /* time step                                     */
     double  qm;    /* charge-to-mass ratio of the mobile species    */
     double  rho0;  /* density of the immobile ion background        */
+    int32_t cg_iters; /* CG iterations for solver 1 (0: the paper's 150) */
+    int32_t pad_;
 } ora_params;
 
 #define TWO32 4294967296.0
@@ -284,6 +286,19 @@ int32_t ora_cg_paper(const ora_params *p, const double *rho, int32_t maxit,
     return it;
 }
 
+/* The field solve of a whole step: the exact periodic solve (reading R2),
+ * or the paper's fixed-iteration CG when the parameters ask for it. */
+static void field_solve(const ora_params *p, const double *rho, double *E)
+{
+    if (p->solver == 1) {
+        double *phi = (double *)malloc(sizeof(double) * (size_t)p->ng);
+        ora_cg_paper(p, rho, p->cg_iters > 0 ? p->cg_iters : 150, phi, E);
+        free(phi);
+    } else {
+        ora_solve(p, rho, E, NULL);
+    }
+}
+
 /* Field at particle positions with the deposit's weights (Sec. 2.3). */
 void ora_gather(const ora_params *p, const double *x, const double *E, double *Ep)
 {
@@ -372,7 +387,7 @@ void ora_step(const ora_params *p, double *x, double *v, double *E, int32_t mode
     ora_gather(p, x, E, Ep);
     ora_push(p, x, v, Ep, acc);
     ora_density(p, x, mode, rho, NULL);
-    ora_solve(p, rho, E, NULL);
+    field_solve(p, rho, E);
     if (row) {
         row[0] = 0.25 * m * (acc[0] + acc[1]);
         row[1] = we;
@@ -390,7 +405,7 @@ void ora_run(const ora_params *p, double *x, double *v, int64_t nsteps, int32_t 
 {
     double *Ep = (double *)malloc(sizeof(double) * (size_t)(p->np > 0 ? p->np : 1));
     ora_density(p, x, mode, rho, NULL);
-    ora_solve(p, rho, E, NULL);
+    field_solve(p, rho, E);
     for (int64_t n = 0; n < nsteps; ++n) {
         if (E_hist)
             memcpy(E_hist + n * p->ng, E, sizeof(double) * (size_t)p->ng);

@@ -36,7 +36,7 @@ struct RunDev {
     int32_t tile;                // particles per tile (multiple of kUnit)
     int32_t ntiles;
     int32_t precision;           // 0 = FP32 state, 1 = FP64 state
-    uint32_t pad0_;
+    int32_t solver;              // 0 = exact prefix-sum solve, 1 = the paper's CG
     uint32_t flags;              // PIC_FLAG_* bits
     double dx;
     double qfac;                 // Q / (dx 2^32): density per unit of S
@@ -48,7 +48,7 @@ struct RunDev {
     double momentum_now;
     int64_t charge_now;          // sum_g S_g of the current positions
     int32_t sort_swap;           // 1 when the sorted copy lives in u_alt/w_alt
-    int32_t pad_;
+    int32_t cg_iters;            // CG iterations (solver 1)
 };
 
 // One unit of schedule: tiles [tile_begin, tile_end) of run `run`, which is
@@ -100,6 +100,10 @@ hipError_t launch_step(RunDev *runs, const WorkItem *items, WorkQueue *queue,
                        int grid, const LaunchShape &shape, int ng_lds, int precision, int prologue,
                        int nsolve, hipStream_t stream, const StepEvents *ev = nullptr);
 
+// The solve launch alone (pic_solve.hip): nsolve workgroups, workgroup b
+// solves runs[b].
+hipError_t launch_solve(RunDev *runs, int nsolve, int prologue, hipStream_t stream);
+
 // The particle pass alone (used by the autotuner on saved state).
 hipError_t launch_particles(RunDev *runs, const WorkItem *items, WorkQueue *queue,
                             int grid, const LaunchShape &shape, int ng_lds, int precision,
@@ -131,6 +135,19 @@ hipError_t sort_prepare();
 // Enqueue a stable sort of run R's particles by cell into its alternate
 // arrays, then swap the arrays in the descriptor (device side).
 hipError_t launch_sort(RunDev *R, int64_t np, int ng, int precision, void *scratch, hipStream_t stream);
+
+// Device-side loader (pic_loader.hip): particle i gets x0 = L u_i,
+// x = wrap(x0 + amp sin(k x0)), v = v0 (-1)^i (two beams) or v0, plus
+// vth n_i, with u_i and n_i drawn from SplitMix64 streams whose bases are
+// given; stored in engine units like the host conversion.
+struct LoaderArgs {
+    double L, dt, amp, k, v0, vth;
+    unsigned long long base_pos, base_v1, base_v2;
+    int32_t two_beams, pad_;
+};
+unsigned long long loader_stream_base(unsigned long long seed, int stream);
+hipError_t launch_loader(void *u, void *w, int64_t np, int ng, int precision, const LoaderArgs &a, int cus,
+                         hipStream_t stream);
 
 // Autotuner (pic_tune.hip).  tune_key names a size class; tune_lookup finds
 // a cached shape; tune_shapes times `launch(shape)` (one particle pass on

@@ -6,9 +6,10 @@
 //     (Sec. 2.3) into a workgroup-private int64 grid in LDS -> merge into the
 //     run's global grid with 64-bit atomics, plus per-tile FP64 partial sums
 //     of the diagnostics;
-//   solve_kernel (one workgroup per run): the periodic Poisson problem and the
-//     central-difference field (Sec. 2.2) in FP64, writing E^{n+1}, the gather
-//     table for the next step and the step's diagnostics.
+//   solve_kernel (pic_solve.hip, one workgroup per run): the periodic
+//     Poisson problem and the central-difference field (Sec. 2.2) in FP64,
+//     writing E^{n+1}, the gather table for the next step and the step's
+//     diagnostics.
 // The kernel boundary orders the merge before the solve, so no device-wide
 // fence or completion counter is needed.
 
@@ -39,8 +40,6 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <typename T> struct Vec;
 template <> struct Vec<float> { using type = f32x4; static constexpr int n = 4; };
 template <> struct Vec<double> { using type = f64x2; static constexpr int n = 2; };
-
-constexpr int kSolveThreads = 256;   // threads that compute in the solve
 
 // Streaming accesses to particle arrays: global address space, non-temporal
 // (each particle is touched once per step).
@@ -171,160 +170,7 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-__device__ __forceinline__ long long wave_sum(long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
 
-// Sum over the first kSolveThreads threads in a fixed order (butterfly inside
-// each wavefront, then wavefront totals in index order); every thread of the
-// block gets the value.  All threads of the block must call it.
-template <typename V>
-__device__ V solve_sum(V v, V *red) {
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && threadIdx.x < kSolveThreads) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    V s = 0;
-    for (int k = 0; k < kSolveThreads / 64; ++k) s += red[k];
-    __syncthreads();
-    return s;
-}
-
-// Exclusive prefix sum over the first kSolveThreads threads in index order.
-__device__ double solve_exclusive_scan(double v, double *red) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double inc = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        double t = __shfl_up(inc, o);
-        if (lane >= o) inc += t;
-    }
-    double exc = __shfl_up(inc, 1);
-    if (lane == 0) exc = 0.0;
-    if (lane == 63 && threadIdx.x < kSolveThreads) red[wv] = inc;
-    __syncthreads();
-    double off = 0.0;
-    for (int k = 0; k < wv && k < kSolveThreads / 64; ++k) off += red[k];
-    __syncthreads();
-    return off + exc;
-}
-
-// Periodic Poisson solve of one run by one workgroup (Sec. 2.2), computed by
-// its first kSolveThreads threads whatever the block size.
-// The face field F_{g+1/2} = -(phi_{g+1} - phi_g)/dx satisfies
-// F_{g+1/2} - F_{g-1/2} = (rho_g - mean rho) dx, so it is a prefix sum;
-// periodicity of phi sets sum_g F_{g+1/2} = 0; the central-difference node
-// field is E_g = (F_{g-1/2} + F_{g+1/2}) / 2.  D: LDS scratch of ng doubles.
-__device__ __noinline__ void solve_run(RunDev *R, double *D, double *red, long long *redi,
-                                       bool prologue) {
-    const int ng = R->ng;
-    const int tid = threadIdx.x;
-    const bool worker = tid < kSolveThreads;
-    unsigned long long *S = R->S;
-    unsigned long long *S_last = R->S_last;
-    // Plain loads: this runs in the launch after the deposit, so the kernel
-    // boundary orders them after every workgroup's merge into S and its tile
-    // partials.
-    // Loads are issued in batches of kBatch so that many are in flight; the
-    // sums keep the strided order g = tid, tid + 256, ...
-    constexpr int kBatch = 16;
-    long long tot = 0;
-    if (worker) {
-        for (int g0 = tid; g0 < ng; g0 += kSolveThreads * kBatch) {
-            unsigned long long sv[kBatch];
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                const int g = g0 + k * kSolveThreads;
-                sv[k] = g < ng ? S[g] : 0ull;
-            }
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                const int g = g0 + k * kSolveThreads;
-                if (g < ng) {
-                    S[g] = 0ull;
-                    S_last[g] = sv[k];
-                    tot += (long long)sv[k];
-                    D[g] = (double)sv[k];
-                }
-            }
-        }
-    }
-    tot = solve_sum(tot, redi);                   // exact: sum_g S_g
-    const double meanS = (double)tot / (double)ng;
-    const double scale = R->qfac * R->dx;         // face-field change per unit of S
-    const int seg = (ng + kSolveThreads - 1) / kSolveThreads;
-    const int g0 = worker ? min(tid * seg, ng) : ng, g1 = min(g0 + seg, ng);
-    double acc = 0.0;
-    for (int g = g0; g < g1; ++g) {
-        acc += (D[g] - meanS) * scale;
-        D[g] = acc;
-    }
-    const double off = solve_exclusive_scan(acc, red);
-    double csum = 0.0;
-    for (int g = g0; g < g1; ++g) {
-        double fv = D[g] + off;
-        D[g] = fv;
-        csum += fv;
-    }
-    const double C = -solve_sum(csum, red) / (double)ng;   // syncs: D complete
-    const double ecoef = R->ecoef;
-    float *Ehat = R->Ehat;
-    double *Ehat64 = R->Ehat64;
-    double *E64 = R->E64;
-    double we = 0.0;
-    if (worker) {
-        for (int g = tid; g < ng; g += kSolveThreads) {
-            double left = D[g == 0 ? ng - 1 : g - 1];
-            double E = 0.5 * (left + D[g]) + C;
-            E64[g] = E;
-            double eh = E * ecoef;
-            Ehat[g] = (float)eh;
-            if (Ehat64) Ehat64[g] = eh;
-            we += E * E;
-        }
-    }
-    we = 0.5 * R->dx * solve_sum(we, red);
-    double a1 = 0.0, a2 = 0.0;
-    const double *part = R->tile_part;
-    const int ntiles = R->ntiles;
-    if (worker) {
-        for (int t0 = tid; t0 < ntiles; t0 += kSolveThreads * kBatch) {
-            f64x2 pv[kBatch];
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                const int t = t0 + k * kSolveThreads;
-                pv[k] = t < ntiles ? *reinterpret_cast<const f64x2 *>(part + kPartCols * t) : f64x2{0.0, 0.0};
-            }
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                a1 += pv[k].x;
-                a2 += pv[k].y;
-            }
-        }
-    }
-    a1 = solve_sum(a1, red);
-    a2 = solve_sum(a2, red);
-    if (tid == 0) {
-        const double kc = R->kcoef, pc = R->pcoef;
-        const double k_new = kc * a1;
-        if (!prologue) {
-            const int64_t n = R->step;
-            if (n < R->hist_cap) {
-                double *row = R->hist + (size_t)kHistCols * (size_t)n;
-                row[0] = 0.5 * (R->kinetic_now + k_new);   // KE^n, time-centred
-                row[1] = R->field_now;                     // W_E^n of the gathered field
-                row[2] = pc * a2;                          // P^{n+1/2}
-                row[3] = k_new;                            // K^{n+1/2}
-            }
-            R->step = n + 1;
-        }
-        R->kinetic_now = k_new;
-        R->momentum_now = pc * a2;
-        R->field_now = we;
-        R->charge_now = (int64_t)tot;
-    }
-}
 
 // Issue the loads of one block: UNROLL vectors of VEC particles per lane,
 // lane-contiguous so each load instruction covers 64*VEC particles.
@@ -572,16 +418,6 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
     }
 }
 
-// Second launch of a step: workgroup b solves run runs[b] for E^{n+1} and
-// records the diagnostics; runs that are idle or finished return at once.
-__global__ __launch_bounds__(kSolveThreads) void solve_kernel(RunDev *runs, int prologue) {
-    __shared__ double D[kMaxNg];
-    __shared__ double red[kSolveThreads / 64];
-    __shared__ long long redi[kSolveThreads / 64];
-    RunDev *R = runs + blockIdx.x;
-    if (!prologue && R->step >= R->step_target) return;
-    solve_run(R, D, red, redi, prologue != 0);
-}
 
 template <typename T, int BLOCK, int UNROLL, bool PUSH>
 const void *kernel_ptr() {
@@ -657,8 +493,7 @@ hipError_t launch_step(RunDev *runs, const WorkItem *items, WorkQueue *queue, in
     e = launch_particles(runs, items, queue, grid, ls, ng_lds, precision, prologue, stream);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev->e1, stream)) != hipSuccess) return e;
-    void *sargs[] = {(void *)&runs, (void *)&prologue};
-    e = hipLaunchKernel((const void *)solve_kernel, dim3(nsolve), dim3(kSolveThreads), sargs, 0, stream);
+    e = launch_solve(runs, nsolve, prologue, stream);
     if (e != hipSuccess) return e;
     if (ev) return hipEventRecord(ev->e2, stream);
     return hipSuccess;

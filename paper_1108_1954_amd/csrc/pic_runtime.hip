@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -101,6 +102,9 @@ pic_status validate(const pic_params *p) {
     if (p->tile < 0 || p->tile % kUnit != 0 || p->tile > (1 << 20))
         return fail(PIC_EINVAL, "tile must be 0 or a multiple of %d up to 2^20 (got %d)", kUnit, p->tile);
     if (p->history_cap < 0) return fail(PIC_EINVAL, "history_cap must be >= 0");
+    if (p->solver != PIC_SOLVE_EXACT && p->solver != PIC_SOLVE_CG_PAPER)
+        return fail(PIC_EINVAL, "solver must be PIC_SOLVE_EXACT or PIC_SOLVE_CG_PAPER (got %d)", p->solver);
+    if (p->cg_iters < 0 || p->cg_iters > 100000) return fail(PIC_EINVAL, "cg_iters must be in [0, 100000]");
     return PIC_OK;
 }
 
@@ -212,6 +216,36 @@ pic_status check_particles(const pic_params *p, const double *x0, const double *
     return PIC_OK;
 }
 
+// A device loader's parameters.  The normal deviates come from 53-bit
+// uniforms, so |n| <= sqrt(-2 ln 2^-53) < 8.58 and |v| <= |v0| + 8.58 vth:
+// the single-wrap contract |v| dt < L is checked on that bound.
+pic_status check_loader(const pic_params *p, const pic_loader *ld) {
+    if (!ld) return fail(PIC_EINVAL, "loader is NULL");
+    if (ld->pos_stream < 0 || ld->vel_stream < 0) return fail(PIC_EINVAL, "loader streams must be >= 0");
+    if (ld->two_beams != 0 && ld->two_beams != 1) return fail(PIC_EINVAL, "two_beams must be 0 or 1");
+    if (!(std::isfinite(ld->amp) && std::isfinite(ld->k) && std::isfinite(ld->v0) && std::isfinite(ld->vth) &&
+          ld->vth >= 0))
+        return fail(PIC_EINVAL, "loader amp, k, v0 must be finite and vth finite and >= 0");
+    if (!((std::fabs(ld->v0) + 8.58 * ld->vth) * p->dt < p->L))
+        return fail(PIC_EINVAL, "loader velocities can exceed L/dt (need (|v0| + 8.58 vth) dt < L)");
+    return PIC_OK;
+}
+
+LoaderArgs loader_args(const pic_params *p, const pic_loader *ld) {
+    LoaderArgs a{};
+    a.L = p->L;
+    a.dt = p->dt;
+    a.amp = ld->amp;
+    a.k = ld->k;
+    a.v0 = ld->v0;
+    a.vth = ld->vth;
+    a.base_pos = loader_stream_base(ld->seed, ld->pos_stream);
+    a.base_v1 = loader_stream_base(ld->seed, ld->vel_stream);
+    a.base_v2 = loader_stream_base(ld->seed, ld->vel_stream + 1);
+    a.two_beams = ld->two_beams;
+    return a;
+}
+
 // Fill the descriptor constants (normalisation of Sec. 2 / Appendix A):
 // Q = sign(qm) rho0 L / np, m = Q/qm, ecoef = qm dt^2/dx, ...
 void fill_constants(pic_run *r) {
@@ -228,7 +262,8 @@ void fill_constants(pic_run *r) {
     h.tile = r->lay.tile;
     h.ntiles = r->lay.ntiles;
     h.precision = p.precision;
-    h.pad0_ = 0;
+    h.solver = p.solver;
+    h.cg_iters = p.cg_iters > 0 ? p.cg_iters : 150;
     h.flags = 0;
     h.dx = r->dx;
     h.qfac = r->Q / (r->dx * 4294967296.0);
@@ -437,14 +472,13 @@ hipError_t dev_read(const pic_run *r, void *dst, const void *src, size_t bytes) 
 
 }  // namespace
 
-extern "C" pic_status pic_create(const pic_params *params, const double *x0, const double *v_mhalf,
-                                 void *dev_mem, size_t dev_bytes, void *stream, pic_run **out) {
-    pic_status st = validate(params);
-    if (st != PIC_OK) return st;
-    if (!out) return fail(PIC_EINVAL, "out is NULL");
-    *out = nullptr;
-    st = check_particles(params, x0, v_mhalf);
-    if (st != PIC_OK) return st;
+namespace {
+
+// Common part of pic_create and pic_create_loaded: memory, descriptor,
+// particles (by `fill`, enqueued on the run's stream), initial deposit and
+// solve, launch shape.
+pic_status create_run(const pic_params *params, void *dev_mem, size_t dev_bytes, void *stream,
+                      const std::function<pic_status(pic_run *)> &fill, pic_run **out) {
     pic_run *r = new pic_run();
     r->p = *params;
     r->lay = make_layout(params);
@@ -480,11 +514,12 @@ extern "C" pic_status pic_create(const pic_params *params, const double *x0, con
     fill_constants(r);
     carve(r);
     r->grid = single_run_grid(r, r->shape, d.cus);
-    st = upload_particles(r, x0, v_mhalf);
+    pic_status st = fill(r);
     if (st == PIC_OK) st = init_device_state(r);
     if (st == PIC_OK) st = choose_shape(r, d);
     if (st != PIC_OK) {
         std::string msg = g_err;
+        (void)hipStreamSynchronize(r->stream);
         if (r->owns_mem) (void)hipFree(r->base);
         delete r;
         g_err = msg;
@@ -492,6 +527,38 @@ extern "C" pic_status pic_create(const pic_params *params, const double *x0, con
     }
     *out = r;
     return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" pic_status pic_create(const pic_params *params, const double *x0, const double *v_mhalf,
+                                 void *dev_mem, size_t dev_bytes, void *stream, pic_run **out) {
+    pic_status st = validate(params);
+    if (st != PIC_OK) return st;
+    if (!out) return fail(PIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    st = check_particles(params, x0, v_mhalf);
+    if (st != PIC_OK) return st;
+    return create_run(params, dev_mem, dev_bytes, stream,
+                      [x0, v_mhalf](pic_run *r) { return upload_particles(r, x0, v_mhalf); }, out);
+}
+
+extern "C" pic_status pic_create_loaded(const pic_params *params, const pic_loader *loader, void *dev_mem,
+                                        size_t dev_bytes, void *stream, pic_run **out) {
+    pic_status st = validate(params);
+    if (st != PIC_OK) return st;
+    if (!out) return fail(PIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    st = check_loader(params, loader);
+    if (st != PIC_OK) return st;
+    const LoaderArgs a = loader_args(params, loader);
+    return create_run(params, dev_mem, dev_bytes, stream,
+                      [&a](pic_run *r) {
+                          HIP_TRY(launch_loader(r->host.u, r->host.w, r->p.np, r->p.ng, r->p.precision, a,
+                                                device_info().cus, r->stream));
+                          return PIC_OK;
+                      },
+                      out);
 }
 
 namespace {
@@ -1155,8 +1222,13 @@ extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream
     return PIC_OK;
 }
 
-extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, const double *x0,
-                                      const double *v_mhalf, int64_t nsteps, int64_t *run_id) {
+namespace {
+
+// Admission: host particles (x0, v_mhalf) converted into pinned staging and
+// uploaded, or (ld) drawn on the device; then grid clearing, descriptor and
+// the initial deposit and solve, all queued on the batch stream.
+pic_status admit_run(pic_batch *b, const pic_params *params, const double *x0, const double *v_mhalf,
+                     const LoaderArgs *ld, int64_t nsteps, int64_t *run_id) {
     pic_status st = batch_check(b);
     if (st != PIC_OK) return st;
     st = validate(params);
@@ -1166,8 +1238,10 @@ extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, co
     if (params->precision != PIC_FP32) return fail(PIC_EINVAL, "batched runs use PIC_FP32 state");
     if (params->ng > b->cfg.ng_max) return fail(PIC_EINVAL, "ng %d exceeds the batch's ng_max %d", params->ng, b->cfg.ng_max);
     if (b->free_slots.empty()) return fail(PIC_EBUDGET, "run table full (%d runs)", b->cfg.max_runs);
-    st = check_particles(params, x0, v_mhalf);
-    if (st != PIC_OK) return st;
+    if (!ld) {
+        st = check_particles(params, x0, v_mhalf);
+        if (st != PIC_OK) return st;
+    }
     Layout lay = make_layout(params);
     size_t off = 0;
     if (!b->arena.alloc(lay.total, &off))
@@ -1191,18 +1265,23 @@ extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, co
     // Convert into pinned staging and queue upload, grid clearing,
     // descriptor and prologue on the batch stream; the host does not wait.
     const size_t desc_bytes = (sizeof(RunDev) + 255) & ~(size_t)255;
-    const size_t part_bytes = (size_t)params->np * lay.esize;
+    const size_t part_bytes = ld ? 0 : (size_t)params->np * lay.esize;
     size_t gi = 0;
     st = get_staging(b, desc_bytes + 2 * part_bytes, &gi);
     if (st == PIC_OK) {
         Staging &g = b->staging[gi];
-        convert_particles(r, x0, v_mhalf, g.host + desc_bytes, g.host + desc_bytes + part_bytes);
+        if (!ld) convert_particles(r, x0, v_mhalf, g.host + desc_bytes, g.host + desc_bytes + part_bytes);
         std::memcpy(g.host, &r->host, sizeof(RunDev));
         g.busy = true;   // from here on the buffer may be read by queued copies
-        hipError_t e = hipMemcpyAsync(r->host.u, g.host + desc_bytes, part_bytes, hipMemcpyHostToDevice, b->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(r->host.w, g.host + desc_bytes + part_bytes, part_bytes, hipMemcpyHostToDevice,
-                               b->stream);
+        hipError_t e;
+        if (ld) {
+            e = launch_loader(r->host.u, r->host.w, params->np, params->ng, PIC_FP32, *ld, b->cus, b->stream);
+        } else {
+            e = hipMemcpyAsync(r->host.u, g.host + desc_bytes, part_bytes, hipMemcpyHostToDevice, b->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(r->host.w, g.host + desc_bytes + part_bytes, part_bytes, hipMemcpyHostToDevice,
+                                   b->stream);
+        }
         if (e == hipSuccess) {
             st = queue_device_init(r, (const RunDev *)g.host);
             if (st != PIC_OK) e = hipErrorUnknown;
@@ -1244,6 +1323,25 @@ extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, co
     b->dirty = true;
     *run_id = m.id;
     return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" pic_status pic_batch_admit(pic_batch *b, const pic_params *params, const double *x0,
+                                      const double *v_mhalf, int64_t nsteps, int64_t *run_id) {
+    return admit_run(b, params, x0, v_mhalf, nullptr, nsteps, run_id);
+}
+
+extern "C" pic_status pic_batch_admit_loaded(pic_batch *b, const pic_params *params, const pic_loader *loader,
+                                             int64_t nsteps, int64_t *run_id) {
+    pic_status st = batch_check(b);
+    if (st != PIC_OK) return st;
+    st = validate(params);
+    if (st != PIC_OK) return st;
+    st = check_loader(params, loader);
+    if (st != PIC_OK) return st;
+    const LoaderArgs a = loader_args(params, loader);
+    return admit_run(b, params, nullptr, nullptr, &a, nsteps, run_id);
 }
 
 namespace {

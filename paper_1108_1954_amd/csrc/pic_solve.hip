@@ -1,0 +1,316 @@
+// Field solve of the PIC step (gfx950): the second launch of every step.
+//
+// Workgroup b solves run runs[b] (idle and finished runs return at once):
+// it takes the fixed-point charge sums S the particle pass merged, clears
+// them for the next step, solves the periodic three-point Poisson problem
+// (Sec. 2.2) exactly, or with the paper's fixed-iteration CG when the run
+// asks for it, forms the central-difference node field, writes E^{n+1} in
+// FP64 and the gather table for the next particle pass, and records the
+// step's diagnostics from the per-tile partial sums.  Every reduction is a
+// fixed-order sum over the workgroup's threads, so the results depend only
+// on the run.
+#include "pic_internal.h"
+
+namespace pic1d {
+
+namespace {
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kSolveThreads = 1024;  // threads of the solve workgroup
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ long long wave_sum(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Sum over the first kSolveThreads threads in a fixed order (butterfly inside
+// each wavefront, then wavefront totals in index order); every thread of the
+// block gets the value.  All threads of the block must call it.
+template <typename V>
+__device__ V solve_sum(V v, V *red) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && threadIdx.x < kSolveThreads) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    V s = 0;
+    for (int k = 0; k < kSolveThreads / 64; ++k) s += red[k];
+    __syncthreads();
+    return s;
+}
+
+// Exclusive prefix sum over the first kSolveThreads threads in index order.
+__device__ double solve_exclusive_scan(double v, double *red) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        double t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    double exc = __shfl_up(inc, 1);
+    if (lane == 0) exc = 0.0;
+    if (lane == 63 && threadIdx.x < kSolveThreads) red[wv] = inc;
+    __syncthreads();
+    double off = 0.0;
+    for (int k = 0; k < wv && k < kSolveThreads / 64; ++k) off += red[k];
+    __syncthreads();
+    return off + exc;
+}
+
+// The paper's field solver (Sec. 2.2, Sec. 3.3): matrix-free conjugate
+// gradient on the three-point system with the potential at node 0 held at
+// zero (its row is the identity, its residual zero), started from zero and
+// run for a fixed number of iterations, then the central-difference field.
+// Thread tid owns nodes tid, tid + 256, ... (up to kMaxNg / 256 of them)
+// and keeps its potential, residual and A d in registers; the search
+// direction d lives in LDS for the stencil.  The dot products are sums in a
+// fixed order.  On entry D[g] holds S_g; on exit D[g] holds E_g.
+constexpr int kCgPer = kMaxNg / kSolveThreads;
+
+__device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, double meanS) {
+    const int ng = R->ng, tid = threadIdx.x;
+    const bool worker = tid < kSolveThreads;
+    const double dx = R->dx, qf = R->qfac;
+    double ph[kCgPer], r[kCgPer], z[kCgPer];
+    double rr = 0.0;
+#pragma unroll
+    for (int k = 0; k < kCgPer; ++k) {
+        const int g = k * kSolveThreads + tid;
+        ph[k] = 0.0;
+        z[k] = 0.0;
+        // rho_g = rho0 + (Q/dx) 2^-32 S_g = (Q/dx) 2^-32 (S_g - mean S): the
+        // run is neutral, sum_g S_g = np 2^32 exactly
+        r[k] = (worker && g > 0 && g < ng) ? -(qf * (D[g] - meanS)) * dx * dx : 0.0;
+        rr += r[k] * r[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kCgPer; ++k) {
+        const int g = k * kSolveThreads + tid;
+        if (worker && g < ng) D[g] = r[k];            // d = r (own nodes only)
+    }
+    rr = solve_sum(rr, red);                          // syncs: d complete
+    if (__builtin_sqrt(rr) > 1e-16) {
+        const int iters = R->cg_iters;
+        for (int it = 0; it < iters; ++it) {
+            double zd = 0.0;
+#pragma unroll
+            for (int k = 0; k < kCgPer; ++k) {
+                const int g = k * kSolveThreads + tid;
+                if (worker && g < ng) {
+                    double zk;
+                    if (g == 0) {
+                        zk = D[0];
+                    } else {
+                        const double right = g + 1 < ng ? D[g + 1] : 0.0;
+                        zk = D[g - 1] - 2.0 * D[g] + right;
+                    }
+                    z[k] = zk;
+                    zd += zk * D[g];
+                }
+            }
+            zd = solve_sum(zd, red);
+            if (zd == 0.0) break;
+            const double alpha = rr / zd;
+            double rn = 0.0;
+#pragma unroll
+            for (int k = 0; k < kCgPer; ++k) {
+                const int g = k * kSolveThreads + tid;
+                if (worker && g < ng) {
+                    ph[k] += alpha * D[g];
+                    r[k] -= alpha * z[k];
+                    rn += r[k] * r[k];
+                }
+            }
+            rn = solve_sum(rn, red);                  // also: every read of d is done
+            const double beta = rn / rr;
+#pragma unroll
+            for (int k = 0; k < kCgPer; ++k) {
+                const int g = k * kSolveThreads + tid;
+                if (worker && g < ng) D[g] = beta * D[g] + r[k];
+            }
+            __syncthreads();
+            rr = rn;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kCgPer; ++k) {
+        const int g = k * kSolveThreads + tid;
+        if (worker && g < ng) D[g] = ph[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kCgPer; ++k) {
+        const int g = k * kSolveThreads + tid;
+        if (worker && g < ng) {
+            const double right = D[g + 1 < ng ? g + 1 : 0];
+            const double left = D[g == 0 ? ng - 1 : g - 1];
+            z[k] = -(right - left) / (2.0 * dx);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kCgPer; ++k) {
+        const int g = k * kSolveThreads + tid;
+        if (worker && g < ng) D[g] = z[k];
+    }
+    __syncthreads();
+}
+
+// Periodic Poisson solve of one run by one workgroup (Sec. 2.2), computed by
+// its first kSolveThreads threads whatever the block size.
+// The face field F_{g+1/2} = -(phi_{g+1} - phi_g)/dx satisfies
+// F_{g+1/2} - F_{g-1/2} = (rho_g - mean rho) dx, so it is a prefix sum;
+// periodicity of phi sets sum_g F_{g+1/2} = 0; the central-difference node
+// field is E_g = (F_{g-1/2} + F_{g+1/2}) / 2.  D: LDS scratch of ng doubles.
+__device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, long long *redi,
+                                       bool prologue) {
+    const int ng = R->ng;
+    const int tid = threadIdx.x;
+    const bool worker = tid < kSolveThreads;
+    unsigned long long *S = R->S;
+    unsigned long long *S_last = R->S_last;
+    // Plain loads: this runs in the launch after the deposit, so the kernel
+    // boundary orders them after every workgroup's merge into S and its tile
+    // partials.
+    // Loads are issued in batches of kBatch so that many are in flight; the
+    // sums keep the strided order g = tid, tid + 256, ...
+    constexpr int kBatch = 16;
+    long long tot = 0;
+    if (worker) {
+        for (int g0 = tid; g0 < ng; g0 += kSolveThreads * kBatch) {
+            unsigned long long sv[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int g = g0 + k * kSolveThreads;
+                sv[k] = g < ng ? S[g] : 0ull;
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int g = g0 + k * kSolveThreads;
+                if (g < ng) {
+                    S[g] = 0ull;
+                    S_last[g] = sv[k];
+                    tot += (long long)sv[k];
+                    D[g] = (double)sv[k];
+                }
+            }
+        }
+    }
+    // tile partials of the diagnostics: loaded now, summed in the same
+    // strided order, so their latency overlaps the solve
+    double a1 = 0.0, a2 = 0.0;
+    const double *part = R->tile_part;
+    const int ntiles = R->ntiles;
+    if (worker) {
+        for (int t0 = tid; t0 < ntiles; t0 += kSolveThreads * kBatch) {
+            f64x2 pv[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int t = t0 + k * kSolveThreads;
+                pv[k] = t < ntiles ? *reinterpret_cast<const f64x2 *>(part + kPartCols * t) : f64x2{0.0, 0.0};
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                a1 += pv[k].x;
+                a2 += pv[k].y;
+            }
+        }
+    }
+    tot = solve_sum(tot, redi);                   // exact: sum_g S_g
+    const double meanS = (double)tot / (double)ng;
+    const bool cg = R->solver == 1;
+    double C = 0.0;
+    if (cg) {
+        __syncthreads();                          // D holds every S_g
+        cg_paper(R, D, red, meanS);               // D: E_g
+    } else {
+        const double scale = R->qfac * R->dx;     // face-field change per unit of S
+        const int seg = (ng + kSolveThreads - 1) / kSolveThreads;
+        const int g0 = worker ? min(tid * seg, ng) : ng, g1 = min(g0 + seg, ng);
+        double acc = 0.0;
+        for (int g = g0; g < g1; ++g) {
+            acc += (D[g] - meanS) * scale;
+            D[g] = acc;
+        }
+        const double off = solve_exclusive_scan(acc, red);
+        double csum = 0.0;
+        for (int g = g0; g < g1; ++g) {
+            double fv = D[g] + off;
+            D[g] = fv;
+            csum += fv;
+        }
+        C = -solve_sum(csum, red) / (double)ng;   // syncs: D complete
+    }
+    const double ecoef = R->ecoef;
+    float *Ehat = R->Ehat;
+    double *Ehat64 = R->Ehat64;
+    double *E64 = R->E64;
+    double we = 0.0;
+    if (worker) {
+        for (int g = tid; g < ng; g += kSolveThreads) {
+            double E;
+            if (cg) {
+                E = D[g];
+            } else {
+                double left = D[g == 0 ? ng - 1 : g - 1];
+                E = 0.5 * (left + D[g]) + C;
+            }
+            E64[g] = E;
+            double eh = E * ecoef;
+            Ehat[g] = (float)eh;
+            if (Ehat64) Ehat64[g] = eh;
+            we += E * E;
+        }
+    }
+    we = 0.5 * R->dx * solve_sum(we, red);
+    a1 = solve_sum(a1, red);
+    a2 = solve_sum(a2, red);
+    if (tid == 0) {
+        const double kc = R->kcoef, pc = R->pcoef;
+        const double k_new = kc * a1;
+        if (!prologue) {
+            const int64_t n = R->step;
+            if (n < R->hist_cap) {
+                double *row = R->hist + (size_t)kHistCols * (size_t)n;
+                row[0] = 0.5 * (R->kinetic_now + k_new);   // KE^n, time-centred
+                row[1] = R->field_now;                     // W_E^n of the gathered field
+                row[2] = pc * a2;                          // P^{n+1/2}
+                row[3] = k_new;                            // K^{n+1/2}
+            }
+            R->step = n + 1;
+        }
+        R->kinetic_now = k_new;
+        R->momentum_now = pc * a2;
+        R->field_now = we;
+        R->charge_now = (int64_t)tot;
+    }
+}
+
+// Second launch of a step: workgroup b solves run runs[b] for E^{n+1} and
+// records the diagnostics; runs that are idle or finished return at once.
+__global__ __launch_bounds__(kSolveThreads) void solve_kernel(RunDev *runs, int prologue) {
+    __shared__ double D[kMaxNg];
+    __shared__ double red[kSolveThreads / 64];
+    __shared__ long long redi[kSolveThreads / 64];
+    RunDev *R = runs + blockIdx.x;
+    if (!prologue && R->step >= R->step_target) return;
+    solve_run(R, D, red, redi, prologue != 0);
+}
+
+}  // namespace
+
+hipError_t launch_solve(RunDev *runs, int nsolve, int prologue, hipStream_t stream) {
+    if (nsolve <= 0) return hipErrorInvalidValue;
+    void *args[] = {(void *)&runs, (void *)&prologue};
+    return hipLaunchKernel((const void *)solve_kernel, dim3(nsolve), dim3(kSolveThreads), args, 0, stream);
+}
+
+}  // namespace pic1d

@@ -115,6 +115,10 @@ class RunSpec:
     rho0: float = 1.0
     name: str = ""
     make: Optional[Callable[[], Tuple[np.ndarray, np.ndarray]]] = field(default=None, repr=False)
+    # the same initial state as a device-loader description (pic_loader
+    # fields), for the set-ups that are a uniform or single-mode-displaced
+    # plasma with beams and a Maxwellian spread
+    loader: Optional[dict] = None
 
     def particles(self) -> Tuple[np.ndarray, np.ndarray]:
         x, v = self.make()
@@ -163,13 +167,16 @@ def two_stream_small(seed: int = 1, np_: int = 10_000, nsteps: int = 200) -> Run
     beams interleaved by particle index.
     """
     L = 2.053
+    k = 2.0 * math.pi / L
 
     def make():
         x0 = L * uniform(seed, 0, np_)
-        x = wrap_positions(x0 + 1e-3 * np.sin(2.0 * math.pi * x0 / L), L)
+        x = wrap_positions(x0 + 1e-3 * np.sin(k * x0), L)
         v = 0.2 * _beam_signs(np_)
         return x, v
-    return RunSpec(L=L, ng=64, np_=np_, dt=0.1, nsteps=nsteps, name="two_stream_ng64_np1e4", make=make)
+    return RunSpec(L=L, ng=64, np_=np_, dt=0.1, nsteps=nsteps, name="two_stream_ng64_np1e4", make=make,
+                   loader=dict(seed=seed, pos_stream=0, vel_stream=1, amp=1e-3, k=k, v0=0.2, vth=0.0,
+                               two_beams=True))
 
 
 def warm_two_stream_large(seed: int = 2, np_: int = 1 << 26, ng: int = 4096,
@@ -241,7 +248,9 @@ def warm_maxwellian_large(seed: int = 5, np_: int = 1 << 28, ng: int = 8192,
         v = 0.1 * normal(seed, 1, np_)
         return x, v
     return RunSpec(L=L, ng=ng, np_=np_, dt=0.05, nsteps=nsteps,
-                   name=f"maxwellian_ng{ng}_np{np_}", make=make)
+                   name=f"maxwellian_ng{ng}_np{np_}", make=make,
+                   loader=dict(seed=seed, pos_stream=0, vel_stream=1, amp=-(1e-2 / k), k=k, v0=0.0, vth=0.1,
+                               two_beams=False))
 
 
 def quiet_two_stream(L: float = 2.053, ng: int = 64, ppc: int = 64, v0: float = 0.2,
@@ -269,3 +278,22 @@ def cold_plasma(L: float = 2.053, ng: int = 64, ppc: int = 64, amp: float = 1e-3
         x = wrap_positions(x0 + amp * L * np.sin(2.0 * math.pi * x0 / L), L)
         return x, np.zeros(n)
     return RunSpec(L=L, ng=ng, np_=n, dt=dt, nsteps=nsteps, name="cold_plasma", make=make)
+
+
+def paper_weak_scaling(cores: int = 128, seed: int = 6, nsteps: int = 1000) -> RunSpec:
+    """The paper's weak-scaling workload (Sec. 5.2 and the appendix's
+    parameters) at the size it reaches on `cores` UPC threads: 64 cells and
+    64,000 particles per thread, L = 3.1415 per thread, Maxwellian vth = 0.2
+    with no drift, dt = 0.1, 1000 cycles.  Positions are seeded uniform (the
+    paper's own start is a lattice)."""
+    L = 3.1415 * cores
+    ng = 64 * cores
+    np_ = 64000 * cores
+
+    def make():
+        x = wrap_positions(L * uniform(seed, 0, np_), L)
+        v = 0.2 * normal(seed, 1, np_)
+        return x, v
+    return RunSpec(L=L, ng=ng, np_=np_, dt=0.1, nsteps=nsteps, name=f"paper_weak_scaling_{cores}", make=make,
+                   loader=dict(seed=seed, pos_stream=0, vel_stream=1, amp=0.0, k=0.0, v0=0.0, vth=0.2,
+                               two_beams=False))

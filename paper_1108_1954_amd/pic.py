@@ -21,10 +21,12 @@ PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_EBUDGET = 0, -1, -2
 PIC_FP32, PIC_FP64 = 0, 1
 PIC_MAX_NG = 8192
 PIC_HIST_COLS = 4
-PIC_FLAG_NONFINITE, PIC_FLAG_MULTIWRAP = 1, 2
+PIC_FLAG_NONFINITE, PIC_FLAG_MULTIWRAP, PIC_FLAG_SORT = 1, 2, 4
+PIC_SOLVE_EXACT, PIC_SOLVE_CG_PAPER = 0, 1
 
 SYMBOLS = (
-    "pic_last_error", "pic_version", "pic_footprint", "pic_create", "pic_sort", "pic_step", "pic_step_graph",
+    "pic_last_error", "pic_version", "pic_footprint", "pic_create", "pic_create_loaded", "pic_sort",
+    "pic_step", "pic_step_graph", "pic_batch_admit_loaded",
     "pic_step_profiled", "pic_batch_step_profiled", "pic_diagnostics", "pic_read_particles", "pic_read_raw", "pic_read_grid", "pic_read_history",
     "pic_destroy", "pic_batch_create", "pic_batch_admit", "pic_batch_step", "pic_batch_poll",
     "pic_batch_run", "pic_batch_release", "pic_batch_usage", "pic_batch_destroy",
@@ -35,7 +37,7 @@ class pic_params(C.Structure):
     _fields_ = [("L", C.c_double), ("ng", C.c_int32), ("precision", C.c_int32),
                 ("np", C.c_int64), ("dt", C.c_double), ("qm", C.c_double),
                 ("rho0", C.c_double), ("sort_every", C.c_int32), ("tile", C.c_int32),
-                ("history_cap", C.c_int64)]
+                ("history_cap", C.c_int64), ("solver", C.c_int32), ("cg_iters", C.c_int32)]
 
 
 class pic_diag(C.Structure):
@@ -46,6 +48,18 @@ class pic_diag(C.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
+class pic_loader(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("pos_stream", C.c_int32), ("vel_stream", C.c_int32),
+                ("amp", C.c_double), ("k", C.c_double), ("v0", C.c_double), ("vth", C.c_double),
+                ("two_beams", C.c_int32), ("pad_", C.c_int32)]
+
+
+def make_loader(seed: int, pos_stream: int = 0, vel_stream: int = 1, amp: float = 0.0, k: float = 0.0,
+                v0: float = 0.0, vth: float = 0.0, two_beams: bool = False) -> pic_loader:
+    return pic_loader(seed=int(seed), pos_stream=int(pos_stream), vel_stream=int(vel_stream), amp=float(amp),
+                      k=float(k), v0=float(v0), vth=float(vth), two_beams=int(bool(two_beams)), pad_=0)
 
 
 class pic_batch_config(C.Structure):
@@ -88,6 +102,8 @@ def load(path: str = LIB_PATH):
     sig = {
         "pic_footprint": [P, C.POINTER(sz)],
         "pic_create": [P, dptr, dptr, vp, sz, vp, C.POINTER(vp)],
+        "pic_create_loaded": [P, C.POINTER(pic_loader), vp, sz, vp, C.POINTER(vp)],
+        "pic_batch_admit_loaded": [vp, P, C.POINTER(pic_loader), i64, C.POINTER(i64)],
         "pic_sort": [vp],
         "pic_step": [vp, i64],
         "pic_step_graph": [vp, i64, i32],
@@ -129,10 +145,10 @@ def _dptr(a: np.ndarray):
 
 def make_params(L: float, ng: int, np: int, dt: float, qm: float = -1.0, rho0: float = 1.0,
                 precision: int = PIC_FP32, sort_every: int = 0, tile: int = 0,
-                history_cap: int = 0) -> pic_params:
+                history_cap: int = 0, solver: int = 0, cg_iters: int = 0) -> pic_params:
     return pic_params(L=float(L), ng=int(ng), precision=int(precision), np=int(np), dt=float(dt),
                       qm=float(qm), rho0=float(rho0), sort_every=int(sort_every), tile=int(tile),
-                      history_cap=int(history_cap))
+                      history_cap=int(history_cap), solver=int(solver), cg_iters=int(cg_iters))
 
 
 def pic_version() -> str:
@@ -155,6 +171,20 @@ def pic_create(params: pic_params, x0, v_mhalf, dev_mem: Optional[int] = None, d
     _check(load().pic_create(C.byref(params), _dptr(x0), _dptr(v), dev_mem, dev_bytes, stream,
                              C.byref(out)))
     return out
+
+
+def pic_create_loaded(params: pic_params, loader: pic_loader, dev_mem: Optional[int] = None, dev_bytes: int = 0,
+                      stream: Optional[int] = None) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(load().pic_create_loaded(C.byref(params), C.byref(loader), dev_mem, int(dev_bytes), stream,
+                                    C.byref(out)))
+    return out
+
+
+def pic_batch_admit_loaded(batch, params: pic_params, loader: pic_loader, nsteps: int) -> int:
+    rid = C.c_int64(0)
+    _check(load().pic_batch_admit_loaded(batch, C.byref(params), C.byref(loader), int(nsteps), C.byref(rid)))
+    return rid.value
 
 
 def pic_sort(run) -> None:
@@ -298,14 +328,19 @@ def current_stream() -> int:
 class Run:
     """A run whose device memory is a torch tensor (kept alive here)."""
 
-    def __init__(self, params: pic_params, x0, v_mhalf, use_torch_memory: bool = True):
+    def __init__(self, params: pic_params, x0=None, v_mhalf=None, use_torch_memory: bool = True,
+                 loader: Optional[pic_loader] = None):
+        """Host particles (x0, v_mhalf), or `loader` to draw them on the device."""
         self.params = params
         self._buf = None
         addr, nbytes = None, 0
         if use_torch_memory:
             nbytes = pic_footprint(params)
             self._buf, addr = device_buffer(nbytes)
-        self.handle = pic_create(params, x0, v_mhalf, addr, nbytes, current_stream())
+        if loader is not None:
+            self.handle = pic_create_loaded(params, loader, addr, nbytes, current_stream())
+        else:
+            self.handle = pic_create(params, x0, v_mhalf, addr, nbytes, current_stream())
 
     def step(self, n: int, graph_steps: int = 0) -> None:
         if graph_steps > 0:

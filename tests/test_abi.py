@@ -4,6 +4,7 @@ work (no compute calls here)."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -38,10 +39,29 @@ def test_library_exports_every_declared_symbol(lib):
     assert P.pic_version().startswith("pic1d")
 
 
-def test_struct_layouts_match_header():
-    assert C.sizeof(P.pic_params) == 64
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the ctypes structs equal the C compiler's
+    for include/pic.h."""
+    assert C.sizeof(P.pic_params) == 72
     assert C.sizeof(P.pic_diag) == 64
     assert C.sizeof(P.pic_batch_config) == 32
+    structs = {"pic_params": P.pic_params, "pic_diag": P.pic_diag, "pic_batch_config": P.pic_batch_config}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pic.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'    printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'    printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
 
 
 def good(**kw):
@@ -54,6 +74,7 @@ def good(**kw):
     dict(ng=1), dict(ng=P.PIC_MAX_NG + 1), dict(np=0), dict(np=1 << 31), dict(L=0.0),
     dict(L=float("nan")), dict(dt=0.0), dict(dt=-1.0), dict(qm=0.0), dict(rho0=0.0),
     dict(precision=2), dict(tile=100), dict(tile=-256), dict(tile=512), dict(history_cap=-1),
+    dict(solver=2), dict(solver=-1), dict(cg_iters=-1), dict(cg_iters=100001),
 ])
 def test_footprint_rejects_invalid_parameters(lib, bad):
     with pytest.raises(P.PicError) as e:
@@ -112,3 +133,18 @@ def test_missing_extension_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(P, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         P.load(str(tmp_path / "absent.so"))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(vth=-0.1), dict(two_beams=2), dict(pos_stream=-1), dict(v0=float("inf")),
+    dict(v0=300.0), dict(vth=5.0),        # (|v0| + 8.58 vth) dt >= L = 2.053 with dt = 0.1
+])
+def test_loader_rejects_invalid_parameters(lib, bad):
+    """Checked on the host before any device work (runs without a GPU)."""
+    d = dict(seed=1, pos_stream=0, vel_stream=1, amp=1e-3, k=3.0, v0=0.2, vth=0.01, two_beams=True)
+    d.update(bad)
+    ld = P.pic_loader(**{k: (int(v) if k in ("seed", "pos_stream", "vel_stream", "two_beams") else float(v))
+                         for k, v in d.items()}, pad_=0)
+    with pytest.raises(P.PicError) as e:
+        P.pic_create_loaded(good(), ld)
+    assert e.value.status == P.PIC_EINVAL

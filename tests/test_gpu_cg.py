@@ -1,0 +1,137 @@
+"""The paper's fixed-iteration CG field solve on the GPU (solver
+PIC_SOLVE_CG_PAPER) against the oracle's ora_cg_paper.
+
+The engine and the oracle perform the same CG operations element by element
+(no FMA contraction on either side); only the two dot products per
+iteration are summed in different orders.  The allowed difference is set
+from the solver's own rounding sensitivity: a second FP64 evaluation of the
+same CG with a third summation order (numpy's pairwise dot) measures how far
+two valid FP64 evaluations drift apart over the iterations, and the GPU must
+stay within a small multiple of that drift (plus a floor of a few ulps of
+max|E|).  Where 150 iterations do not converge (ng >= 256) the unconverged
+field itself is the result being reproduced.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1108_1954_amd import inputs as I
+from paper_1108_1954_amd import pic as P
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    P.load()
+    yield
+
+
+def cg_numpy(rho, dx, iters):
+    """The same CG as ora_cg_paper with numpy's summation order (sensitivity
+    estimate only; the reference is the oracle)."""
+    ng = rho.size
+    phi = np.zeros(ng)
+    r = -rho * dx * dx
+    r[0] = 0.0
+    d = r.copy()
+    rr = float(np.dot(r, r))
+    if np.sqrt(rr) > 1e-16:
+        for _ in range(iters):
+            z = np.empty(ng)
+            z[0] = d[0]
+            right = np.append(d[2:], 0.0)
+            z[1:] = d[:-1][:ng - 1] - 2.0 * d[1:] + right
+            zd = float(np.dot(z, d))
+            if zd == 0.0:
+                break
+            alpha = rr / zd
+            phi += alpha * d
+            r -= alpha * z
+            rn = float(np.dot(r, r))
+            d = (rn / rr) * d + r
+            rr = rn
+    return -(np.roll(phi, -1) - np.roll(phi, 1)) / (2.0 * dx)
+
+
+@pytest.mark.parametrize("ng", [64, 256, 2048, 8192])
+def test_cg_field_matches_oracle_cg(ng):
+    print(f"CG solve parity ng={ng}", flush=True)
+    L = 0.032 * ng
+    np_ = 50 * ng
+    x = L * I.uniform(ng, 0, np_)
+    v = 0.1 * I.normal(ng, 1, np_)
+    p = P.make_params(L, ng, np_, 0.1, solver=P.PIC_SOLVE_CG_PAPER, cg_iters=150)
+    with P.Run(p, x, v) as r:                      # creation deposits x^0 and solves for E^0
+        S, E, _ = r.grid()
+    op = O.params(L, ng, np_, dt=0.1)
+    rho = O.density_fixed(op, S)
+    _, E_ora, it = O.cg_paper(op, rho, maxit=150)
+    E_np = cg_numpy(rho, L / ng, 150)
+    scale = np.abs(E_ora).max()
+    spread = np.abs(E_np - E_ora).max()
+    err = np.abs(E - E_ora).max()
+    print(f"  |E_gpu - E_oracle| = {err / scale:.3e} max|E|; numpy-order spread {spread / scale:.3e}; "
+          f"oracle iterations {it}", flush=True)
+    assert err <= 10 * spread + 16 * ng * EPS64 * scale
+    if ng <= 128:                                 # converged: the exact solve as well
+        E_ex, _ = O.solve(op, rho)
+        assert np.abs(E - E_ex).max() <= 1e-8 * np.abs(E_ex).max()
+
+
+def test_cg_run_history_matches_oracle_run_with_cg():
+    """A two-stream run (ng = 64, the paper's verification case) stepped with
+    the CG solver: the engine's field-energy history against the oracle's
+    steps with the same solver."""
+    spec = I.two_stream_small(nsteps=100)
+    x, v = spec.particles()
+    p = P.make_params(spec.L, spec.ng, spec.np_, spec.dt, history_cap=spec.nsteps,
+                      solver=P.PIC_SOLVE_CG_PAPER)
+    with P.Run(p, x, v) as r:
+        r.step(spec.nsteps, graph_steps=10)
+        h = r.history()
+        ms_particle, ms_solve = P.pic_step_profiled(r.handle, 5)
+    op = O.params(spec.L, spec.ng, spec.np_, dt=spec.dt, solver=O.SOLVE_CG_PAPER, cg_iters=150)
+    ref = O.run(op, x, v, spec.nsteps, mode=O.DEPOSIT_PLAIN)["hist"]
+    err = np.abs(h[:, 1] - ref[:, 1]).max() / ref[:, 1].max()
+    print(f"CG run W_E vs oracle CG run: {err:.3e}; CG solve {ms_solve * 1e3:.1f} us per step "
+          f"(particle pass {ms_particle * 1e3:.1f} us)", flush=True)
+    assert err < 1e-3
+
+
+def test_unconverged_cg_differs_from_exact_solve_and_batches_alike():
+    """At ng = 2048 the 150-iteration CG field differs from the exact one
+    (the paper's solver really is used), and a CG run in a batch is
+    bit-identical to the same run alone."""
+    specs = I.ensemble(nruns=3, seed=21, nsteps=12, np_scale=0.02)
+    s = max(specs, key=lambda q: q.ng)
+    x, v = s.particles()
+    pe = P.make_params(s.L, s.ng, s.np_, s.dt, history_cap=s.nsteps)
+    pc = P.make_params(s.L, s.ng, s.np_, s.dt, history_cap=s.nsteps, solver=P.PIC_SOLVE_CG_PAPER)
+    with P.Run(pe, x, v) as a, P.Run(pc, x, v) as b:
+        a.step(s.nsteps)
+        b.step(s.nsteps)
+        Ea, Eb = a.grid()[1], b.grid()[1]
+        hist_alone, raw_alone = b.history(), b.raw()
+    if s.ng >= 256:
+        assert np.abs(Ea - Eb).max() > 1e-3 * np.abs(Ea).max()
+    bt = P.pic_batch_create(1 << 30, 2048, max_runs=8, graph_steps=4, stream=P.current_stream())
+    try:
+        ids = []
+        for q in specs:
+            xq, vq = (x, v) if q is s else q.particles()
+            solver = P.PIC_SOLVE_CG_PAPER if q is s else P.PIC_SOLVE_EXACT
+            ids.append(P.pic_batch_admit(bt, P.make_params(q.L, q.ng, q.np_, q.dt, history_cap=q.nsteps,
+                                                           solver=solver), xq, vq, q.nsteps))
+        P.pic_batch_step(bt, 100)
+        view = P.pic_batch_run(bt, ids[specs.index(s)])
+        np.testing.assert_array_equal(P.pic_read_history(view, 0, s.nsteps), hist_alone)
+        u, w = P.pic_read_raw(view, s.np_)
+        np.testing.assert_array_equal(u, raw_alone[0])
+        np.testing.assert_array_equal(w, raw_alone[1])
+    finally:
+        P.pic_batch_destroy(bt)

@@ -212,6 +212,24 @@ def test_paper_cg_150_iterations_unconverged_at_large_grid():
     assert rel > 0.1
 
 
+def test_run_with_paper_cg_equals_exact_solve_when_converged():
+    """Whole oracle steps with the paper's CG selected (reading R2's
+    alternative): at ng = 32 the 150 iterations exceed ng - 1, the CG
+    converges, and 20 steps of the two-stream case agree with the exact
+    solver up to the CG's convergence residue; at ng = 512 they do not."""
+    s = I.two_stream_small(nsteps=20)
+    x, v = s.particles()
+    out = {}
+    for ng in (32, 512):
+        for solver in (O.SOLVE_EXACT, O.SOLVE_CG_PAPER):
+            p = O.params(s.L, ng, s.np_, dt=s.dt, solver=solver)
+            out[ng, solver] = O.run(p, x, v, s.nsteps, mode=O.DEPOSIT_PLAIN)["hist"][:, 1]
+    ex, cg = out[32, O.SOLVE_EXACT], out[32, O.SOLVE_CG_PAPER]
+    np.testing.assert_allclose(cg, ex, rtol=1e-8)
+    ex, cg = out[512, O.SOLVE_EXACT], out[512, O.SOLVE_CG_PAPER]
+    assert np.max(np.abs(cg - ex) / ex) > 1e-3
+
+
 # ----------------------------------------------------------------- gather ---
 
 def test_gather_on_nodes_and_linear_field():
