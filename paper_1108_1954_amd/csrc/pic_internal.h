@@ -101,8 +101,8 @@ hipError_t launch_step(RunDev *runs, const WorkItem *items, WorkQueue *queue,
                        int nsolve, hipStream_t stream, const StepEvents *ev = nullptr);
 
 // The solve launch alone (pic_solve.hip): nsolve workgroups, workgroup b
-// solves runs[b].
-hipError_t launch_solve(RunDev *runs, int nsolve, int prologue, hipStream_t stream);
+// solves runs[b]; ng_max bounds the ng of every run in the launch.
+hipError_t launch_solve(RunDev *runs, int nsolve, int prologue, int ng_max, hipStream_t stream);
 
 // The particle pass alone (used by the autotuner on saved state).
 hipError_t launch_particles(RunDev *runs, const WorkItem *items, WorkQueue *queue,

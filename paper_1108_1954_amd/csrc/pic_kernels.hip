@@ -493,7 +493,7 @@ hipError_t launch_step(RunDev *runs, const WorkItem *items, WorkQueue *queue, in
     e = launch_particles(runs, items, queue, grid, ls, ng_lds, precision, prologue, stream);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev->e1, stream)) != hipSuccess) return e;
-    e = launch_solve(runs, nsolve, prologue, stream);
+    e = launch_solve(runs, nsolve, prologue, ng_lds, stream);
     if (e != hipSuccess) return e;
     if (ev) return hipEventRecord(ev->e2, stream);
     return hipSuccess;

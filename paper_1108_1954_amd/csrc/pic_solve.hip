@@ -17,7 +17,16 @@ namespace {
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kSolveThreads = 1024;  // threads of the solve workgroup
+constexpr int kMaxSolveThreads = 1024;  // largest solve workgroup
+
+// Threads that work on a run's solve: a function of ng alone (so results
+// depend only on the run), at least 256 and enough that every thread owns
+// at most 8 nodes.  A launch covering several runs uses the largest; the
+// extra waves of smaller runs only take part in the barriers.
+__host__ __device__ __forceinline__ int solve_threads(int ng) {
+    const int t = (ng + 8 * 64 - 1) / (8 * 64) * 64;
+    return t < 256 ? 256 : (t > kMaxSolveThreads ? kMaxSolveThreads : t);
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -31,22 +40,22 @@ __device__ __forceinline__ long long wave_sum(long long v) {
     return v;
 }
 
-// Sum over the first kSolveThreads threads in a fixed order (butterfly inside
+// Sum over the first nthr threads in a fixed order (butterfly inside
 // each wavefront, then wavefront totals in index order); every thread of the
 // block gets the value.  All threads of the block must call it.
 template <typename V>
-__device__ V solve_sum(V v, V *red) {
+__device__ V solve_sum(V v, V *red, int nthr) {
     v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && threadIdx.x < kSolveThreads) red[threadIdx.x >> 6] = v;
+    if ((threadIdx.x & 63) == 0 && (int)threadIdx.x < nthr) red[threadIdx.x >> 6] = v;
     __syncthreads();
     V s = 0;
-    for (int k = 0; k < kSolveThreads / 64; ++k) s += red[k];
+    for (int k = 0; k < nthr / 64; ++k) s += red[k];
     __syncthreads();
     return s;
 }
 
-// Exclusive prefix sum over the first kSolveThreads threads in index order.
-__device__ double solve_exclusive_scan(double v, double *red) {
+// Exclusive prefix sum over the first nthr threads in index order.
+__device__ double solve_exclusive_scan(double v, double *red, int nthr) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double inc = v;
 #pragma unroll
@@ -56,10 +65,10 @@ __device__ double solve_exclusive_scan(double v, double *red) {
     }
     double exc = __shfl_up(inc, 1);
     if (lane == 0) exc = 0.0;
-    if (lane == 63 && threadIdx.x < kSolveThreads) red[wv] = inc;
+    if (lane == 63 && (int)threadIdx.x < nthr) red[wv] = inc;
     __syncthreads();
     double off = 0.0;
-    for (int k = 0; k < wv && k < kSolveThreads / 64; ++k) off += red[k];
+    for (int k = 0; k < wv && k < nthr / 64; ++k) off += red[k];
     __syncthreads();
     return off + exc;
 }
@@ -72,17 +81,17 @@ __device__ double solve_exclusive_scan(double v, double *red) {
 // and keeps its potential, residual and A d in registers; the search
 // direction d lives in LDS for the stencil.  The dot products are sums in a
 // fixed order.  On entry D[g] holds S_g; on exit D[g] holds E_g.
-constexpr int kCgPer = kMaxNg / kSolveThreads;
+constexpr int kCgPer = 8;   // nodes per thread: ng <= 8 solve_threads(ng)
 
-__device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, double meanS) {
+__device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, double meanS, int nthr) {
     const int ng = R->ng, tid = threadIdx.x;
-    const bool worker = tid < kSolveThreads;
+    const bool worker = tid < nthr;
     const double dx = R->dx, qf = R->qfac;
     double ph[kCgPer], r[kCgPer], z[kCgPer];
     double rr = 0.0;
 #pragma unroll
     for (int k = 0; k < kCgPer; ++k) {
-        const int g = k * kSolveThreads + tid;
+        const int g = k * nthr + tid;
         ph[k] = 0.0;
         z[k] = 0.0;
         // rho_g = rho0 + (Q/dx) 2^-32 S_g = (Q/dx) 2^-32 (S_g - mean S): the
@@ -92,17 +101,17 @@ __device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, doub
     }
 #pragma unroll
     for (int k = 0; k < kCgPer; ++k) {
-        const int g = k * kSolveThreads + tid;
+        const int g = k * nthr + tid;
         if (worker && g < ng) D[g] = r[k];            // d = r (own nodes only)
     }
-    rr = solve_sum(rr, red);                          // syncs: d complete
+    rr = solve_sum(rr, red, nthr);                          // syncs: d complete
     if (__builtin_sqrt(rr) > 1e-16) {
         const int iters = R->cg_iters;
         for (int it = 0; it < iters; ++it) {
             double zd = 0.0;
 #pragma unroll
             for (int k = 0; k < kCgPer; ++k) {
-                const int g = k * kSolveThreads + tid;
+                const int g = k * nthr + tid;
                 if (worker && g < ng) {
                     double zk;
                     if (g == 0) {
@@ -115,24 +124,24 @@ __device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, doub
                     zd += zk * D[g];
                 }
             }
-            zd = solve_sum(zd, red);
+            zd = solve_sum(zd, red, nthr);
             if (zd == 0.0) break;
             const double alpha = rr / zd;
             double rn = 0.0;
 #pragma unroll
             for (int k = 0; k < kCgPer; ++k) {
-                const int g = k * kSolveThreads + tid;
+                const int g = k * nthr + tid;
                 if (worker && g < ng) {
                     ph[k] += alpha * D[g];
                     r[k] -= alpha * z[k];
                     rn += r[k] * r[k];
                 }
             }
-            rn = solve_sum(rn, red);                  // also: every read of d is done
+            rn = solve_sum(rn, red, nthr);                  // also: every read of d is done
             const double beta = rn / rr;
 #pragma unroll
             for (int k = 0; k < kCgPer; ++k) {
-                const int g = k * kSolveThreads + tid;
+                const int g = k * nthr + tid;
                 if (worker && g < ng) D[g] = beta * D[g] + r[k];
             }
             __syncthreads();
@@ -142,13 +151,13 @@ __device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, doub
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kCgPer; ++k) {
-        const int g = k * kSolveThreads + tid;
+        const int g = k * nthr + tid;
         if (worker && g < ng) D[g] = ph[k];
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kCgPer; ++k) {
-        const int g = k * kSolveThreads + tid;
+        const int g = k * nthr + tid;
         if (worker && g < ng) {
             const double right = D[g + 1 < ng ? g + 1 : 0];
             const double left = D[g == 0 ? ng - 1 : g - 1];
@@ -158,14 +167,14 @@ __device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, doub
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kCgPer; ++k) {
-        const int g = k * kSolveThreads + tid;
+        const int g = k * nthr + tid;
         if (worker && g < ng) D[g] = z[k];
     }
     __syncthreads();
 }
 
 // Periodic Poisson solve of one run by one workgroup (Sec. 2.2), computed by
-// its first kSolveThreads threads whatever the block size.
+// its first solve_threads(ng) threads whatever the block size.
 // The face field F_{g+1/2} = -(phi_{g+1} - phi_g)/dx satisfies
 // F_{g+1/2} - F_{g-1/2} = (rho_g - mean rho) dx, so it is a prefix sum;
 // periodicity of phi sets sum_g F_{g+1/2} = 0; the central-difference node
@@ -174,7 +183,8 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
                                        bool prologue) {
     const int ng = R->ng;
     const int tid = threadIdx.x;
-    const bool worker = tid < kSolveThreads;
+    const int nthr = solve_threads(ng);
+    const bool worker = tid < nthr;
     unsigned long long *S = R->S;
     unsigned long long *S_last = R->S_last;
     // Plain loads: this runs in the launch after the deposit, so the kernel
@@ -185,16 +195,16 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
     constexpr int kBatch = 16;
     long long tot = 0;
     if (worker) {
-        for (int g0 = tid; g0 < ng; g0 += kSolveThreads * kBatch) {
+        for (int g0 = tid; g0 < ng; g0 += nthr * kBatch) {
             unsigned long long sv[kBatch];
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
-                const int g = g0 + k * kSolveThreads;
+                const int g = g0 + k * nthr;
                 sv[k] = g < ng ? S[g] : 0ull;
             }
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
-                const int g = g0 + k * kSolveThreads;
+                const int g = g0 + k * nthr;
                 if (g < ng) {
                     S[g] = 0ull;
                     S_last[g] = sv[k];
@@ -210,11 +220,11 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
     const double *part = R->tile_part;
     const int ntiles = R->ntiles;
     if (worker) {
-        for (int t0 = tid; t0 < ntiles; t0 += kSolveThreads * kBatch) {
+        for (int t0 = tid; t0 < ntiles; t0 += nthr * kBatch) {
             f64x2 pv[kBatch];
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
-                const int t = t0 + k * kSolveThreads;
+                const int t = t0 + k * nthr;
                 pv[k] = t < ntiles ? *reinterpret_cast<const f64x2 *>(part + kPartCols * t) : f64x2{0.0, 0.0};
             }
 #pragma unroll
@@ -224,30 +234,30 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
             }
         }
     }
-    tot = solve_sum(tot, redi);                   // exact: sum_g S_g
+    tot = solve_sum(tot, redi, nthr);                   // exact: sum_g S_g
     const double meanS = (double)tot / (double)ng;
     const bool cg = R->solver == 1;
     double C = 0.0;
     if (cg) {
         __syncthreads();                          // D holds every S_g
-        cg_paper(R, D, red, meanS);               // D: E_g
+        cg_paper(R, D, red, meanS, nthr);               // D: E_g
     } else {
         const double scale = R->qfac * R->dx;     // face-field change per unit of S
-        const int seg = (ng + kSolveThreads - 1) / kSolveThreads;
+        const int seg = (ng + nthr - 1) / nthr;
         const int g0 = worker ? min(tid * seg, ng) : ng, g1 = min(g0 + seg, ng);
         double acc = 0.0;
         for (int g = g0; g < g1; ++g) {
             acc += (D[g] - meanS) * scale;
             D[g] = acc;
         }
-        const double off = solve_exclusive_scan(acc, red);
+        const double off = solve_exclusive_scan(acc, red, nthr);
         double csum = 0.0;
         for (int g = g0; g < g1; ++g) {
             double fv = D[g] + off;
             D[g] = fv;
             csum += fv;
         }
-        C = -solve_sum(csum, red) / (double)ng;   // syncs: D complete
+        C = -solve_sum(csum, red, nthr) / (double)ng;   // syncs: D complete
     }
     const double ecoef = R->ecoef;
     float *Ehat = R->Ehat;
@@ -255,7 +265,7 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
     double *E64 = R->E64;
     double we = 0.0;
     if (worker) {
-        for (int g = tid; g < ng; g += kSolveThreads) {
+        for (int g = tid; g < ng; g += nthr) {
             double E;
             if (cg) {
                 E = D[g];
@@ -270,9 +280,9 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
             we += E * E;
         }
     }
-    we = 0.5 * R->dx * solve_sum(we, red);
-    a1 = solve_sum(a1, red);
-    a2 = solve_sum(a2, red);
+    we = 0.5 * R->dx * solve_sum(we, red, nthr);
+    a1 = solve_sum(a1, red, nthr);
+    a2 = solve_sum(a2, red, nthr);
     if (tid == 0) {
         const double kc = R->kcoef, pc = R->pcoef;
         const double k_new = kc * a1;
@@ -296,10 +306,10 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
 
 // Second launch of a step: workgroup b solves run runs[b] for E^{n+1} and
 // records the diagnostics; runs that are idle or finished return at once.
-__global__ __launch_bounds__(kSolveThreads) void solve_kernel(RunDev *runs, int prologue) {
+__global__ __launch_bounds__(kMaxSolveThreads) void solve_kernel(RunDev *runs, int prologue) {
     __shared__ double D[kMaxNg];
-    __shared__ double red[kSolveThreads / 64];
-    __shared__ long long redi[kSolveThreads / 64];
+    __shared__ double red[kMaxSolveThreads / 64];
+    __shared__ long long redi[kMaxSolveThreads / 64];
     RunDev *R = runs + blockIdx.x;
     if (!prologue && R->step >= R->step_target) return;
     solve_run(R, D, red, redi, prologue != 0);
@@ -307,10 +317,10 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(RunDev *runs, int 
 
 }  // namespace
 
-hipError_t launch_solve(RunDev *runs, int nsolve, int prologue, hipStream_t stream) {
-    if (nsolve <= 0) return hipErrorInvalidValue;
+hipError_t launch_solve(RunDev *runs, int nsolve, int prologue, int ng_max, hipStream_t stream) {
+    if (nsolve <= 0 || ng_max < 2 || ng_max > kMaxNg) return hipErrorInvalidValue;
     void *args[] = {(void *)&runs, (void *)&prologue};
-    return hipLaunchKernel((const void *)solve_kernel, dim3(nsolve), dim3(kSolveThreads), args, 0, stream);
+    return hipLaunchKernel((const void *)solve_kernel, dim3(nsolve), dim3(solve_threads(ng_max)), args, 0, stream);
 }
 
 }  // namespace pic1d
