@@ -40,22 +40,33 @@ __device__ __forceinline__ long long wave_sum(long long v) {
     return v;
 }
 
-// Sum over the first nthr threads in a fixed order (butterfly inside
-// each wavefront, then wavefront totals in index order); every thread of the
-// block gets the value.  All threads of the block must call it.
+// Block reductions.  Each one writes its wavefront totals to one of two
+// alternating LDS buffers and needs a single barrier: the next reduction
+// writes the other buffer, and the one after that (the same buffer again)
+// runs only after every thread has passed the next reduction's barrier, so
+// after every read of this one.  `par` selects the buffer and must follow
+// the same sequence in every thread.
+constexpr int kRedSlots = kMaxSolveThreads / 64;
+
+// Sum over the first nthr threads in a fixed order (butterfly inside each
+// wavefront, then wavefront totals in index order); every thread gets the
+// value.  All threads of the block must call it.
 template <typename V>
-__device__ V solve_sum(V v, V *red, int nthr) {
+__device__ V solve_sum(V v, V *red2, int &par, int nthr) {
+    V *red = red2 + kRedSlots * par;
+    par ^= 1;
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0 && (int)threadIdx.x < nthr) red[threadIdx.x >> 6] = v;
     __syncthreads();
     V s = 0;
     for (int k = 0; k < nthr / 64; ++k) s += red[k];
-    __syncthreads();
     return s;
 }
 
 // Exclusive prefix sum over the first nthr threads in index order.
-__device__ double solve_exclusive_scan(double v, double *red, int nthr) {
+__device__ double solve_exclusive_scan(double v, double *red2, int &par, int nthr) {
+    double *red = red2 + kRedSlots * par;
+    par ^= 1;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double inc = v;
 #pragma unroll
@@ -69,7 +80,6 @@ __device__ double solve_exclusive_scan(double v, double *red, int nthr) {
     __syncthreads();
     double off = 0.0;
     for (int k = 0; k < wv && k < nthr / 64; ++k) off += red[k];
-    __syncthreads();
     return off + exc;
 }
 
@@ -83,7 +93,7 @@ __device__ double solve_exclusive_scan(double v, double *red, int nthr) {
 // fixed order.  On entry D[g] holds S_g; on exit D[g] holds E_g.
 constexpr int kCgPer = 8;   // nodes per thread: ng <= 8 solve_threads(ng)
 
-__device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, double meanS, int nthr) {
+__device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, int &par, double meanS, int nthr) {
     const int ng = R->ng, tid = threadIdx.x;
     const bool worker = tid < nthr;
     const double dx = R->dx, qf = R->qfac;
@@ -104,7 +114,7 @@ __device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, doub
         const int g = k * nthr + tid;
         if (worker && g < ng) D[g] = r[k];            // d = r (own nodes only)
     }
-    rr = solve_sum(rr, red, nthr);                          // syncs: d complete
+    rr = solve_sum(rr, red, par, nthr);                          // syncs: d complete
     if (__builtin_sqrt(rr) > 1e-16) {
         const int iters = R->cg_iters;
         for (int it = 0; it < iters; ++it) {
@@ -124,7 +134,7 @@ __device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, doub
                     zd += zk * D[g];
                 }
             }
-            zd = solve_sum(zd, red, nthr);
+            zd = solve_sum(zd, red, par, nthr);
             if (zd == 0.0) break;
             const double alpha = rr / zd;
             double rn = 0.0;
@@ -137,7 +147,7 @@ __device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, doub
                     rn += r[k] * r[k];
                 }
             }
-            rn = solve_sum(rn, red, nthr);                  // also: every read of d is done
+            rn = solve_sum(rn, red, par, nthr);                  // also: every read of d is done
             const double beta = rn / rr;
 #pragma unroll
             for (int k = 0; k < kCgPer; ++k) {
@@ -185,6 +195,7 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
     const int tid = threadIdx.x;
     const int nthr = solve_threads(ng);
     const bool worker = tid < nthr;
+    int par = 0, pari = 0;                         // reduction buffers (see solve_sum)
     unsigned long long *S = R->S;
     unsigned long long *S_last = R->S_last;
     // Plain loads: this runs in the launch after the deposit, so the kernel
@@ -234,13 +245,13 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
             }
         }
     }
-    tot = solve_sum(tot, redi, nthr);                   // exact: sum_g S_g
+    tot = solve_sum(tot, redi, pari, nthr);                   // exact: sum_g S_g
     const double meanS = (double)tot / (double)ng;
     const bool cg = R->solver == 1;
     double C = 0.0;
     if (cg) {
         __syncthreads();                          // D holds every S_g
-        cg_paper(R, D, red, meanS, nthr);               // D: E_g
+        cg_paper(R, D, red, par, meanS, nthr);               // D: E_g
     } else {
         const double scale = R->qfac * R->dx;     // face-field change per unit of S
         const int seg = (ng + nthr - 1) / nthr;
@@ -250,14 +261,14 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
             acc += (D[g] - meanS) * scale;
             D[g] = acc;
         }
-        const double off = solve_exclusive_scan(acc, red, nthr);
+        const double off = solve_exclusive_scan(acc, red, par, nthr);
         double csum = 0.0;
         for (int g = g0; g < g1; ++g) {
             double fv = D[g] + off;
             D[g] = fv;
             csum += fv;
         }
-        C = -solve_sum(csum, red, nthr) / (double)ng;   // syncs: D complete
+        C = -solve_sum(csum, red, par, nthr) / (double)ng;   // syncs: D complete
     }
     const double ecoef = R->ecoef;
     float *Ehat = R->Ehat;
@@ -280,9 +291,9 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
             we += E * E;
         }
     }
-    we = 0.5 * R->dx * solve_sum(we, red, nthr);
-    a1 = solve_sum(a1, red, nthr);
-    a2 = solve_sum(a2, red, nthr);
+    we = 0.5 * R->dx * solve_sum(we, red, par, nthr);
+    a1 = solve_sum(a1, red, par, nthr);
+    a2 = solve_sum(a2, red, par, nthr);
     if (tid == 0) {
         const double kc = R->kcoef, pc = R->pcoef;
         const double k_new = kc * a1;
@@ -308,8 +319,8 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
 // records the diagnostics; runs that are idle or finished return at once.
 __global__ __launch_bounds__(kMaxSolveThreads) void solve_kernel(RunDev *runs, int prologue) {
     __shared__ double D[kMaxNg];
-    __shared__ double red[kMaxSolveThreads / 64];
-    __shared__ long long redi[kMaxSolveThreads / 64];
+    __shared__ double red[2 * kRedSlots];
+    __shared__ long long redi[2 * kRedSlots];
     RunDev *R = runs + blockIdx.x;
     if (!prologue && R->step >= R->step_target) return;
     solve_run(R, D, red, redi, prologue != 0);
