@@ -83,6 +83,7 @@ def _bind(L):
     L.ora_density.argtypes = [P, dp, C.c_int32, dp, C.c_void_p]
     L.ora_step.argtypes = [P, dp, dp, dp, C.c_int32, dp, dp, C.c_void_p]
     L.ora_run.argtypes = [P, dp, dp, C.c_int64, C.c_int32, dp, dp, C.c_void_p, C.c_void_p]
+    L.ora_run_literal.argtypes = [P, dp, dp, C.c_int64, C.c_int32, dp, dp]
     return L
 
 
@@ -204,3 +205,14 @@ def run(p: Params, x, v, nsteps: int, mode: int = DEPOSIT_PLAIN, keep_E: bool = 
     if keep_E:
         out["E_hist"] = E_hist
     return out
+
+
+def run_literal(p: Params, x, v, ncycles: int, mode: int = DEPOSIT_PLAIN):
+    """``ncycles`` cycles in the appendix's order (drift, wrap, deposit,
+    solve, gather, kick) from (x, v); returns final x, v, E."""
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    E = np.empty(p.ng)
+    rho = np.empty(p.ng)
+    lib().ora_run_literal(C.byref(p), x, v, int(ncycles), int(mode), E, rho)
+    return dict(x=x, v=v, E=E)

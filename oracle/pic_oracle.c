@@ -413,3 +413,26 @@ void ora_run(const ora_params *p, double *x, double *v, int64_t nsteps, int32_t 
     }
     free(Ep);
 }
+
+/* The cycle in the appendix's own order: drift with the current velocity,
+ * wrap, deposit, solve, then gather and kick (the initial velocity is used
+ * for the first drift; there is no half-step back-push).  Runs `ncycles`
+ * cycles from (x, v) and leaves the final positions, velocities and field.
+ * It differs from ora_run only in where the leapfrog starts: N cycles here
+ * equal one drift, N - 1 steps of ora_run and a closing gather and kick
+ * (the reading of the leapfrog start; pinned by the tests). */
+void ora_run_literal(const ora_params *p, double *x, double *v, int64_t ncycles, int32_t mode,
+                     double *E, double *rho)
+{
+    double *Ep = (double *)malloc(sizeof(double) * (size_t)(p->np > 0 ? p->np : 1));
+    for (int64_t n = 0; n < ncycles; ++n) {
+        for (int64_t i = 0; i < p->np; ++i)
+            x[i] = wrap_position(p, x[i] + v[i] * p->dt);
+        ora_density(p, x, mode, rho, NULL);
+        field_solve(p, rho, E);
+        ora_gather(p, x, E, Ep);
+        for (int64_t i = 0; i < p->np; ++i)
+            v[i] = v[i] + p->qm * Ep[i] * p->dt;
+    }
+    free(Ep);
+}

@@ -297,3 +297,19 @@ def paper_weak_scaling(cores: int = 128, seed: int = 6, nsteps: int = 1000) -> R
     return RunSpec(L=L, ng=ng, np_=np_, dt=0.1, nsteps=nsteps, name=f"paper_weak_scaling_{cores}", make=make,
                    loader=dict(seed=seed, pos_stream=0, vel_stream=1, amp=0.0, k=0.0, v0=0.0, vth=0.2,
                                two_beams=False))
+
+
+def warm_maxwellian_small(seed: int = 7, waves: int = 2, ng: int = 256, ppc: int = 800, vth: float = 0.1,
+                          k: float = 0.5, alpha: float = 1e-2, dt: float = 0.05, nsteps: int = 400) -> RunSpec:
+    """A small warm Maxwellian plasma for the Bohm-Gross frequency: `waves`
+    wavelengths of k in the box, quiet start (lattice) displaced to a density
+    perturbation alpha cos(k x), seeded Maxwellian velocities."""
+    L = waves * 2.0 * math.pi / k
+    n = ng * ppc
+
+    def make():
+        x0 = (np.arange(n) + 0.5) * (L / n)
+        x = wrap_positions(x0 - (alpha / k) * np.sin(k * x0), L)
+        v = vth * normal(seed, 1, n)
+        return x, v
+    return RunSpec(L=L, ng=ng, np_=n, dt=dt, nsteps=nsteps, name="warm_maxwellian_small", make=make)

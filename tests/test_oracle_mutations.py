@@ -37,6 +37,8 @@ MUTANTS = [
     ("cell key half-cell shift sign", "double j = floor(u - 0.5);", "double j = floor(u + 0.5);"),
     ("cell order not stable", "for (int64_t i = 0; i < np; ++i)\n        perm[",
      "for (int64_t i = np - 1; i >= 0; --i)\n        perm["),
+    ("literal cycle kicks with the wrong sign", "            v[i] = v[i] + p->qm * Ep[i] * p->dt;",
+     "            v[i] = v[i] - p->qm * Ep[i] * p->dt;"),
 ]
 
 # The pins run against every build (argument lists for the parametrised ones).
@@ -57,6 +59,8 @@ PINS = [
     (T.test_single_particle_feels_no_self_force, [(0.123,), (1.777,)]),
     (T.test_energy_conservation_two_stream, [()]),
     (T.test_cold_plasma_oscillates_at_the_discrete_plasma_frequency, [()]),
+    (T.test_literal_cycle_order_equals_api_leapfrog_from_drifted_start, [()]),
+    (T.test_warm_plasma_oscillates_at_the_bohm_gross_frequency, [()]),
 ]
 
 

@@ -422,3 +422,44 @@ def test_two_stream_growth_rate():
     m = (t >= t[i01] - 12) & (t <= t[i01] - 4)
     g_we = np.polyfit(t[m], 0.5 * np.log(we[m]), 1)[0]
     assert abs(g_we / g_th - 1) < 0.02
+
+
+# ----------------------------------------------- leapfrog start, warm plasma ---
+
+def test_literal_cycle_order_equals_api_leapfrog_from_drifted_start():
+    """Reading of the leapfrog start: the appendix's cycle (drift with the
+    current velocity, wrap, deposit, solve, gather, kick) run N times from
+    (x0, v0) equals, bit for bit, one drift of x0 with v0, then N - 1 steps
+    of the engine's order started from (x1, v0) with v0 taken as the
+    half-step velocity, then a closing gather and kick."""
+    s = I.two_stream_small(np_=2000, nsteps=25)
+    x0, v0 = s.particles()
+    p = O.params(s.L, 32, s.np_, dt=s.dt)
+    lit = O.run_literal(p, x0, v0, s.nsteps)
+    x1, v1, _ = O.push(p, x0, v0, np.zeros(s.np_))     # drift with v0 (no field)
+    assert np.array_equal(v1, v0)
+    out = O.run(p, x1, v1, s.nsteps - 1)
+    Ep = O.gather(p, out["x"], out["E"])
+    v_end = out["v"] + p.qm * Ep * p.dt
+    np.testing.assert_array_equal(lit["x"], out["x"])
+    np.testing.assert_array_equal(lit["v"], v_end)
+    np.testing.assert_array_equal(lit["E"], out["E"])
+
+
+def test_warm_plasma_oscillates_at_the_bohm_gross_frequency():
+    """A warm Maxwellian (vth = 0.1, k = 0.5, k lambda_D = 0.05) with a
+    loaded cos(kx) density perturbation: the field energy oscillates at twice
+    omega = sqrt(1 + 3 k^2 vth^2) (Bohm-Gross), corrected for the leapfrog's
+    dispersion 2/dt asin(omega dt/2); Landau damping is negligible here."""
+    s = I.warm_maxwellian_small(ppc=200)
+    x, v = s.particles()
+    p = O.params(s.L, s.ng, s.np_, dt=s.dt)
+    we = O.run(p, x, v, s.nsteps)["hist"][:, 1]
+    y = we - we.mean()
+    peaks = [i for i in range(1, len(y) - 1) if y[i] > y[i - 1] and y[i] >= y[i + 1] and y[i] > 0]
+    t = [(i + 0.5 * (y[i - 1] - y[i + 1]) / (y[i - 1] - 2 * y[i] + y[i + 1])) * s.dt for i in peaks]
+    omega = math.pi * (len(t) - 1) / (t[-1] - t[0])
+    w_bg = math.sqrt(1 + 3 * 0.5 ** 2 * 0.1 ** 2)
+    w_lf = 2 / s.dt * math.asin(w_bg * s.dt / 2)
+    assert len(peaks) >= 5
+    assert abs(omega / w_lf - 1) < 2e-3, (omega, w_lf)
