@@ -1,0 +1,118 @@
+"""Edge cases of the batch and the run API on the GPU: the largest grid in a
+batch, releasing an unfinished run and reusing its slot and memory,
+admission errors, and a history shorter than the run."""
+import numpy as np
+import pytest
+
+from paper_1108_1954_amd import inputs as I
+from paper_1108_1954_amd import pic as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    P.load()
+    yield
+
+
+def alone(spec, x, v, nsteps):
+    p = P.make_params(spec.L, spec.ng, spec.np_, spec.dt, history_cap=nsteps)
+    with P.Run(p, x, v) as r:
+        r.step(nsteps)
+        return r.raw(), r.history()
+
+
+def test_batch_at_the_largest_grid_mixes_ng_8192_and_64():
+    big = I.warm_two_stream_large(np_=300_001, ng=8192, nsteps=12, L=0.032 * 8192)
+    small = I.two_stream_small(np_=5_003, nsteps=12)
+    parts = [big.particles(), small.particles()]
+    ref = [alone(s, x, v, s.nsteps) for s, (x, v) in zip((big, small), parts)]
+    b = P.pic_batch_create(1 << 30, P.PIC_MAX_NG, max_runs=4, graph_steps=4, stream=P.current_stream())
+    try:
+        ids = [P.pic_batch_admit(b, P.make_params(s.L, s.ng, s.np_, s.dt, history_cap=s.nsteps), x, v, s.nsteps)
+               for s, (x, v) in zip((big, small), parts)]
+        P.pic_batch_step(b, 50)
+        for rid, s, (raw, hist) in zip(ids, (big, small), ref):
+            view = P.pic_batch_run(b, rid)
+            u, w = P.pic_read_raw(view, s.np_)
+            np.testing.assert_array_equal(u, raw[0])
+            np.testing.assert_array_equal(w, raw[1])
+            np.testing.assert_array_equal(P.pic_read_history(view, 0, s.nsteps), hist)
+    finally:
+        P.pic_batch_destroy(b)
+
+
+def test_release_of_an_unfinished_run_frees_its_slot_and_memory():
+    """A run released before its last step stops; a new run admitted into
+    the freed slot and arena span gives the same result as alone."""
+    a = I.two_stream_small(np_=40_000, nsteps=500)
+    c = I.warm_maxwellian_large(np_=50_003, ng=256, nsteps=17)
+    xa, va = a.particles()
+    xc, vc = c.particles()
+    foot = P.pic_footprint(P.make_params(a.L, a.ng, a.np_, a.dt, history_cap=a.nsteps))
+    b = P.pic_batch_create(foot + (1 << 20), 2048, max_runs=1, graph_steps=4, stream=P.current_stream())
+    try:
+        ra = P.pic_batch_admit(b, P.make_params(a.L, a.ng, a.np_, a.dt, history_cap=a.nsteps), xa, va, a.nsteps)
+        P.pic_batch_step(b, 9)
+        with pytest.raises(P.PicBudget):                 # table full (one slot) and arena full
+            P.pic_batch_admit(b, P.make_params(c.L, c.ng, c.np_, c.dt, history_cap=c.nsteps), xc, vc, c.nsteps)
+        d, _, _ = P.pic_diagnostics(P.pic_batch_run(b, ra))
+        assert d["step"] == 9
+        P.pic_batch_release(b, ra)
+        assert P.pic_batch_usage(b) == (0, P.pic_batch_usage(b)[1], 0)
+        rc = P.pic_batch_admit(b, P.make_params(c.L, c.ng, c.np_, c.dt, history_cap=c.nsteps), xc, vc, c.nsteps)
+        P.pic_batch_step(b, 40)
+        import torch
+        torch.cuda.synchronize()
+        assert P.pic_batch_poll(b) == [rc]
+        view = P.pic_batch_run(b, rc)
+        raw, hist = alone(c, xc, vc, c.nsteps)
+        u, w = P.pic_read_raw(view, c.np_)
+        np.testing.assert_array_equal(u, raw[0])
+        np.testing.assert_array_equal(w, raw[1])
+        np.testing.assert_array_equal(P.pic_read_history(view, 0, c.nsteps), hist)
+    finally:
+        P.pic_batch_destroy(b)
+
+
+def test_admission_errors_leave_the_batch_usable():
+    s = I.two_stream_small(np_=3_000, nsteps=5)
+    x, v = s.particles()
+    b = P.pic_batch_create(1 << 26, 32, max_runs=2, graph_steps=0, stream=P.current_stream())
+    try:
+        with pytest.raises(P.PicError) as e:                # ng 64 > ng_max 32
+            P.pic_batch_admit(b, P.make_params(s.L, s.ng, s.np_, s.dt), x, v, s.nsteps)
+        assert e.value.status == P.PIC_EINVAL
+        with pytest.raises(P.PicError) as e:                # batches hold FP32 state
+            P.pic_batch_admit(b, P.make_params(s.L, 32, s.np_, s.dt, precision=P.PIC_FP64), x, v, s.nsteps)
+        assert e.value.status == P.PIC_EINVAL
+        xb = x.copy()
+        xb[7] = s.L                                          # outside [0, L)
+        with pytest.raises(P.PicError) as e:
+            P.pic_batch_admit(b, P.make_params(s.L, 32, s.np_, s.dt), xb, v, s.nsteps)
+        assert e.value.status == P.PIC_EINVAL
+        rid = P.pic_batch_admit(b, P.make_params(s.L, 32, s.np_, s.dt), x, v, s.nsteps)
+        P.pic_batch_step(b, 10)
+        d, _, _ = P.pic_diagnostics(P.pic_batch_run(b, rid))
+        assert d["step"] == s.nsteps and d["charge_fixed_sum"] == s.np_ << 32
+    finally:
+        P.pic_batch_destroy(b)
+
+
+def test_history_shorter_than_the_run():
+    s = I.two_stream_small(np_=4_000, nsteps=30)
+    x, v = s.particles()
+    full = P.make_params(s.L, s.ng, s.np_, s.dt, history_cap=s.nsteps)
+    short = P.make_params(s.L, s.ng, s.np_, s.dt, history_cap=10)
+    with P.Run(full, x, v) as a, P.Run(short, x, v) as b:
+        a.step(s.nsteps)
+        b.step(s.nsteps)
+        np.testing.assert_array_equal(b.history(0, 10), a.history(0, 10))
+        with pytest.raises(P.PicError) as e:
+            b.history(5, 10)                                 # rows 10..14 were never kept
+        assert e.value.status == P.PIC_EINVAL
+        for ra, rb in zip(a.raw(), b.raw()):
+            np.testing.assert_array_equal(ra, rb)
