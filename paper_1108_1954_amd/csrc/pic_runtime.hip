@@ -112,10 +112,16 @@ pic_status validate(const pic_params *p) {
 // schedule sees the same tiles (and the same diagnostic summation order).
 // At least 1024 (a full vector block for every unroll), at most 16384, and
 // about np/1024 otherwise so that large runs give every wavefront a tile.
+// Default tile (a function of np only, so a run is tiled alike everywhere):
+// about 4096 tiles per run, so that a large single run gives the device's
+// wavefronts a tile each (one tile per wavefront at a time); at least 2048
+// particles from 1M particles on (fewer per-tile start-ups when many runs
+// share the device), at least 1024 and at most 16384 (whole block units).
 int default_tile(int64_t np) {
-    int64_t t = 1024;
-    while (t < 16384 && t * 1024 < np) t *= 2;
-    return (int)t;
+    const int64_t per = (np + 4095) / 4096;
+    int64_t t = (per + kUnit - 1) / kUnit * kUnit;
+    t = std::max<int64_t>(t, np >= ((int64_t)1 << 20) ? 2 * kUnit : kUnit);
+    return (int)std::min<int64_t>(16384, t);
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -354,11 +360,9 @@ pic_status init_device_state(pic_run *r) {
     return PIC_OK;
 }
 
-// Workgroups of a single run's particle pass: enough to give each wavefront
-// a tile, at least 16K particles per workgroup (fewer workgroups merging into
-// the same grid for small runs), at most what is resident at once.
 // Copy a run's particle arrays to/from a scratch buffer (autotuning runs
-// real particle passes on the run's own state and then puts it back).
+// real particle passes on the run's own state and then puts it back; the
+// tile partials those passes write are rewritten by the next real pass).
 pic_status save_particles(const pic_run *r, char *dst, bool restore) {
     const size_t bytes = (size_t)r->p.np * r->lay.esize;
     char *u = (char *)r->cur_u(), *w = (char *)r->cur_w();
@@ -375,6 +379,9 @@ pic_status save_particles(const pic_run *r, char *dst, bool restore) {
     return PIC_OK;
 }
 
+// Workgroups of a single run's particle pass: enough to give each wavefront
+// a tile, at least 16K particles per workgroup (fewer workgroups merging into
+// the same grid for small runs), at most what is resident at once.
 int single_run_grid(const pic_run *r, const LaunchShape &shape, int cus) {
     const int occ = step_occupancy(shape, r->p.ng, r->p.precision);
     const int waves = shape.block / 64;
