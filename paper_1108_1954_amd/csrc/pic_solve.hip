@@ -92,8 +92,107 @@ __device__ double solve_exclusive_scan(double v, double *red2, int &par, int nth
 // direction d lives in LDS for the stencil.  The dot products are sums in a
 // fixed order.  On entry D[g] holds S_g; on exit D[g] holds E_g.
 constexpr int kCgPer = 8;   // nodes per thread: ng <= 8 solve_threads(ng)
+constexpr int kCgWaveMaxNg = 64 * kCgPer;   // grids one wavefront solves alone
+
+// The same CG on one wavefront, for ng <= 512: lane l owns nodes l, l + 64,
+// ...; the dot products are wavefront butterflies and the stencil reads the
+// direction d from LDS written by the same wavefront (LDS operations of a
+// wavefront complete in order), so no workgroup barrier is needed.
+__device__ __forceinline__ void cg_paper_wave(RunDev *R, double *D, double meanS) {
+    const int ng = R->ng, lane = threadIdx.x & 63;
+    const double dx = R->dx, qf = R->qfac;
+    double ph[kCgPer], r[kCgPer], z[kCgPer];
+    double rr = 0.0;
+#pragma unroll
+    for (int k = 0; k < kCgPer; ++k) {
+        const int g = k * 64 + lane;
+        ph[k] = 0.0;
+        z[k] = 0.0;
+        r[k] = (g > 0 && g < ng) ? -(qf * (D[g] - meanS)) * dx * dx : 0.0;
+        rr += r[k] * r[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < kCgPer; ++k) {
+        const int g = k * 64 + lane;
+        if (g < ng) D[g] = r[k];
+    }
+    rr = wave_sum(rr);
+    __builtin_amdgcn_wave_barrier();
+    if (__builtin_sqrt(rr) > 1e-16) {
+        const int iters = R->cg_iters;
+        for (int it = 0; it < iters; ++it) {
+            double zd = 0.0;
+#pragma unroll
+            for (int k = 0; k < kCgPer; ++k) {
+                const int g = k * 64 + lane;
+                if (g < ng) {
+                    double zk;
+                    if (g == 0) {
+                        zk = D[0];
+                    } else {
+                        const double right = g + 1 < ng ? D[g + 1] : 0.0;
+                        zk = D[g - 1] - 2.0 * D[g] + right;
+                    }
+                    z[k] = zk;
+                    zd += zk * D[g];
+                }
+            }
+            zd = wave_sum(zd);
+            if (zd == 0.0) break;
+            const double alpha = rr / zd;
+            double rn = 0.0;
+#pragma unroll
+            for (int k = 0; k < kCgPer; ++k) {
+                const int g = k * 64 + lane;
+                if (g < ng) {
+                    ph[k] += alpha * D[g];
+                    r[k] -= alpha * z[k];
+                    rn += r[k] * r[k];
+                }
+            }
+            rn = wave_sum(rn);
+            const double beta = rn / rr;
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < kCgPer; ++k) {
+                const int g = k * 64 + lane;
+                if (g < ng) D[g] = beta * D[g] + r[k];
+            }
+            __builtin_amdgcn_wave_barrier();
+            rr = rn;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < kCgPer; ++k) {
+        const int g = k * 64 + lane;
+        if (g < ng) D[g] = ph[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < kCgPer; ++k) {
+        const int g = k * 64 + lane;
+        if (g < ng) {
+            const double right = D[g + 1 < ng ? g + 1 : 0];
+            const double left = D[g == 0 ? ng - 1 : g - 1];
+            z[k] = -(right - left) / (2.0 * dx);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < kCgPer; ++k) {
+        const int g = k * 64 + lane;
+        if (g < ng) D[g] = z[k];
+    }
+}
 
 __device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, int &par, double meanS, int nthr) {
+    if (R->ng <= kCgWaveMaxNg) {
+        if (threadIdx.x < 64) cg_paper_wave(R, D, meanS);
+        __syncthreads();                              // D: E_g, for every wavefront
+        return;
+    }
     const int ng = R->ng, tid = threadIdx.x;
     const bool worker = tid < nthr;
     const double dx = R->dx, qf = R->qfac;
