@@ -10,6 +10,9 @@
     oscillation of the loaded k = 0.5 mode must have the Bohm-Gross frequency
     with the leapfrog correction; with the stored oracle history, the FP32
     and FP64-state paths are both compared with it.
+  * The batched ensemble (256 runs, ~1.45e8 particles) in the launch
+    configuration the benchmark times: exact charge for every run, sampled
+    runs' deposits bit-exact, fields and one step within the rounding bounds.
 
 Inputs are the seeded generators of paper_1108_1954_amd.inputs.
 """
@@ -121,3 +124,64 @@ def test_warm_maxwellian_langmuir_frequency_and_precision():
               f"FP64 state {e64:.3e}", flush=True)
         assert e64 <= e32
         assert e32 < 1e-2
+
+
+def test_full_ensemble_in_the_bench_configuration():
+    """The batched ensemble at full size (256 runs, ~1.45e8 particles), in
+    the launch configuration bench.py times (persistent particle pass with
+    the autotuned shape, graph replay of 20 steps): every run keeps its exact
+    charge and raises no flag; on sampled runs the deposit of the downloaded
+    state is bit-exact against the oracle, the field matches the oracle's
+    solve of it, and one more step of sampled particles matches the oracle's
+    gather and push within the rounding bound."""
+    from concurrent.futures import ThreadPoolExecutor
+    import test_gpu_parity as G
+    from oracle import oracle as O
+    specs = I.ensemble(nruns=256, seed=3, nsteps=500)
+    with ThreadPoolExecutor(16) as ex:
+        parts = list(ex.map(lambda s: s.particles(), specs))
+    params = [P.make_params(s.L, s.ng, s.np_, s.dt) for s in specs]
+    budget = int(sum(P.pic_footprint(p) for p in params) * 1.05) + (64 << 20)
+    b = P.pic_batch_create(budget, max(s.ng for s in specs), max_runs=len(specs), graph_steps=20,
+                           stream=P.current_stream())
+    try:
+        ids = [P.pic_batch_admit(b, p, x, v, 100) for p, (x, v) in zip(params, parts)]
+        del parts
+        P.pic_batch_step(b, 20)
+        for rid, s in zip(ids, specs):
+            d, _, _ = P.pic_diagnostics(P.pic_batch_run(b, rid))
+            assert d["step"] == 20 and d["flags"] == 0
+            assert d["charge_fixed_sum"] == s.np_ << 32
+        order = np.argsort([s.np_ for s in specs])
+        sample = sorted(set(int(order[k]) for k in np.linspace(0, len(specs) - 1, 8).astype(int)))
+        rng = np.random.default_rng(0)
+        state = {}
+        for k in sample:
+            s, p, view = specs[k], params[k], P.pic_batch_run(b, ids[k])
+            u0, w0 = P.pic_read_raw(view, s.np_)
+            S0, E0, Eh0 = P.pic_read_grid(view, s.ng)
+            np.testing.assert_array_equal(S0, O.deposit_fixed(s.ng, u0.astype(np.float64)))
+            op = G.oracle_params(p)
+            E_ora, _ = O.solve(op, O.density_fixed(op, S0))
+            np.testing.assert_allclose(E0, E_ora, rtol=0, atol=G.solve_tolerance(p, S0))
+            pick = rng.choice(s.np_, size=min(s.np_, 200_000), replace=False)
+            state[k] = (u0[pick], w0[pick], E_ora, np.abs(Eh0).max(), pick)
+        P.pic_batch_step(b, 1)
+        for k in sample:
+            s, p, view = specs[k], params[k], P.pic_batch_run(b, ids[k])
+            u0, w0, E_ora, eh_max, pick = state[k]
+            u1, w1 = P.pic_read_raw(view, s.np_)
+            dx = s.L / s.ng
+            ops = O.params(s.L, s.ng, pick.size, dt=s.dt)
+            x0 = u0.astype(np.float64) * dx
+            v0 = w0.astype(np.float64) * dx / s.dt
+            x1, v1, _ = O.push(ops, x0, v0, O.gather(ops, x0, E_ora))
+            du, dw = G.push_tolerance(x1 / dx, v1 * s.dt / dx, eh_max, s.ng, G.EPS32)
+            assert np.all(np.abs(w1[pick].astype(np.float64) - v1 * s.dt / dx) <= dw), k
+            assert np.all(np.abs(G.periodic_diff(u1[pick], x1 / dx, s.ng)) <= du), k
+            S1, _, _ = P.pic_read_grid(view, s.ng)
+            np.testing.assert_array_equal(S1, O.deposit_fixed(s.ng, u1.astype(np.float64)))
+        print(f"full ensemble: {len(specs)} runs, {sum(s.np_ for s in specs)} particles; "
+              f"sampled runs {sample} checked", flush=True)
+    finally:
+        P.pic_batch_destroy(b)
