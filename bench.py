@@ -130,8 +130,8 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the engine shards across GPUs "
-              "only by design (see the design notes), no multi-GPU path is measured.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): there is no multi-GPU path "
+              "to run; how runs and particles would shard across GPUs is a design note only.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1108_1954_amd import inputs as I
