@@ -253,6 +253,11 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
     constexpr int PER = 64 * VEC * UNROLL;
     constexpr int SPB = kUnit / PER;                 // sub-blocks per block unit
     static_assert(kUnit % PER == 0, "a block unit holds whole sub-blocks");
+    // Register sets in the load pipeline: three at one vector per lane
+    // (87 VGPRs, five waves per SIMD), two when the sub-blocks are wider
+    // (a third would spill at 1024 threads).  Four sets at one vector cost
+    // a wave per SIMD and measured slower.
+    constexpr int DEPTH = UNROLL == 1 ? 3 : 2;
     const int ng = R->ng;
     const int64_t np = R->np;
     const int ntiles = R->ntiles;
@@ -282,30 +287,41 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
         if (t >= te) break;
         double a1 = 0.0, a2 = 0.0;
         // Full units of the tile in sub-blocks of PER particles,
-        // software-pipelined over two register sets: the loads of the next
-        // sub-block are issued before the current one is processed and
-        // stored, so a wave waits for one load latency per sub-block and
-        // never for its own stores.  Pairs of sub-blocks with unconditional
-        // loads (the load after the last pair re-reads the last sub-block,
-        // in bounds), so every iteration issues the same memory operations.
+        // software-pipelined over DEPTH register sets: sub-block i lives in
+        // set i mod DEPTH, and its loads are issued DEPTH - 1 sub-blocks
+        // before it is processed and stored, so a wave has that many loads
+        // in flight and never waits for its own stores.  Rounds of DEPTH
+        // sub-blocks with unconditional loads (loads past the end re-read the
+        // last sub-block, in bounds, into sets that are not used again), so
+        // every round issues the same memory operations.
         const int64_t nunits = t < nfull ? (nfull - 1 - t) / ntiles + 1 : 0;
         const int64_t nb = nunits * SPB;
         auto sub = [&](int64_t q) -> int64_t {
             return ((int64_t)t + (q / SPB) * ntiles) * kUnit + (q % SPB) * PER;
         };
-        V au[UNROLL], aw[UNROLL], bu[UNROLL], bw[UNROLL];
-        if (nb > 0) load_block<V, VEC, UNROLL>(U, W, sub(0), lane, au, aw);
-        const int64_t npairs = nb / 2;
-        for (int64_t q = 0; q < npairs; ++q) {
-            const int64_t b0 = sub(2 * q), b1 = sub(2 * q + 1), b2 = sub(min(2 * q + 2, nb - 1));
-            load_block<V, VEC, UNROLL>(U, W, b1, lane, bu, bw);
-            run_block<T, V, VEC, UNROLL, PUSH>(U, W, b0, lane, au, aw, Et, Sl, ng, ngf, hi, a1, a2, flags);
-            load_block<V, VEC, UNROLL>(U, W, b2, lane, au, aw);
-            run_block<T, V, VEC, UNROLL, PUSH>(U, W, b1, lane, bu, bw, Et, Sl, ng, ngf, hi, a1, a2, flags);
+        V bu[DEPTH][UNROLL], bw[DEPTH][UNROLL];
+        if (nb > 0) {
+#pragma unroll
+            for (int d = 0; d < DEPTH - 1; ++d)
+                load_block<V, VEC, UNROLL>(U, W, sub(min((int64_t)d, nb - 1)), lane, bu[d], bw[d]);
         }
-        if (nb & 1)
-            run_block<T, V, VEC, UNROLL, PUSH>(U, W, sub(nb - 1), lane, au, aw, Et, Sl, ng, ngf, hi, a1, a2,
-                                               flags);
+        const int64_t nrounds = nb / DEPTH;
+        for (int64_t q = 0; q < nrounds; ++q) {
+#pragma unroll
+            for (int d = 0; d < DEPTH; ++d) {
+                const int64_t ahead = min(q * DEPTH + d + DEPTH - 1, nb - 1);
+                load_block<V, VEC, UNROLL>(U, W, sub(ahead), lane, bu[(d + DEPTH - 1) % DEPTH],
+                                           bw[(d + DEPTH - 1) % DEPTH]);
+                run_block<T, V, VEC, UNROLL, PUSH>(U, W, sub(q * DEPTH + d), lane, bu[d], bw[d], Et, Sl, ng, ngf,
+                                                   hi, a1, a2, flags);
+            }
+        }
+        const int64_t rest = nb - nrounds * DEPTH;
+#pragma unroll
+        for (int d = 0; d < DEPTH - 1; ++d)
+            if (d < rest)
+                run_block<T, V, VEC, UNROLL, PUSH>(U, W, sub(nrounds * DEPTH + d), lane, bu[d], bw[d], Et, Sl, ng,
+                                                   ngf, hi, a1, a2, flags);
         // The run's partial last unit belongs to tile nfull mod ntiles: same
         // per-lane order as a full unit; whole vectors where they fit, then
         // single particles.
