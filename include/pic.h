@@ -147,12 +147,16 @@ pic_status pic_create(const pic_params *params, const double *x0, const double *
  * 0x9E3779B97F4A7C15; uniforms u = (draw >> 11) 2^-53; normals
  * n = sqrt(-2 log1p(-u)) cos(2 pi u') from draws i of streams vel_stream
  * and vel_stream + 1.  Particle i:
- *   x0 = L u_i (stream pos_stream),  x = x0 + amp sin(k x0) wrapped to [0, L),
- *   v^{-1/2} = v0 (-1)^i if two_beams else v0, plus vth n_i,
+ *   x0 = L u_i (stream pos_stream), or the lattice x0 = (i + 1/2) L / np,
+ *   x = x0 + amp sin(k x0) wrapped to [0, L),
+ *   v^{-1/2} = s_i v0 + vth n_i with the beam sign s_i of `beams`,
  * a uniform or single-mode-displaced plasma with drifting beams and a
- * Maxwellian spread (the loads of Sec. 4 and the appendix).  A host can
- * reproduce every value; device sin/log1p/cos may differ from a host
- * library's in the last bit. */
+ * Maxwellian spread (the loads of Sec. 4 and the appendix).  The lattice is
+ * the appendix's quiet start: with np a multiple of ng it puts np/ng
+ * particles at the centres of equal sub-intervals of every cell.  Random
+ * beam signs are the appendix's: +v0 when a uniform u''_i (stream
+ * vel_stream + 2) is below 1/2.  A host can reproduce every value; device
+ * sin/log1p/cos may differ from a host library's in the last bit. */
 typedef struct pic_loader {
     uint64_t seed;
     int32_t  pos_stream;   /* stream of the position uniforms              */
@@ -161,9 +165,15 @@ typedef struct pic_loader {
     double   k;            /* its wavenumber                               */
     double   v0;           /* drift speed                                  */
     double   vth;          /* thermal spread, >= 0                         */
-    int32_t  two_beams;    /* 1: drift +v0 for even i, -v0 for odd i       */
-    int32_t  pad_;
+    int32_t  beams;        /* PIC_BEAMS_*: the beam sign s_i                */
+    int32_t  lattice;      /* 1: lattice positions, 0: uniform random       */
 } pic_loader;
+
+enum {
+    PIC_BEAMS_ONE = 0,        /* s_i = 1: one drifting (or resting) species     */
+    PIC_BEAMS_ALTERNATE = 1,  /* s_i = +1 for even i, -1 for odd i              */
+    PIC_BEAMS_RANDOM = 2      /* s_i = +1 if u''_i < 1/2, else -1               */
+};
 
 /* pic_create with the particles drawn on the device by `loader` (no host
  * arrays, no upload).  EINVAL if (|v0| + 8.58 vth) dt >= L: the normals are

@@ -142,8 +142,8 @@ hipError_t launch_sort(RunDev *R, int64_t np, int ng, int precision, void *scrat
 // given; stored in engine units like the host conversion.
 struct LoaderArgs {
     double L, dt, amp, k, v0, vth;
-    unsigned long long base_pos, base_v1, base_v2;
-    int32_t two_beams, pad_;
+    unsigned long long base_pos, base_v1, base_v2, base_sign;
+    int32_t beams, lattice;
 };
 unsigned long long loader_stream_base(unsigned long long seed, int stream);
 hipError_t launch_loader(void *u, void *w, int64_t np, int ng, int precision, const LoaderArgs &a, int cus,

@@ -8,12 +8,15 @@
 // draw.  Uniforms are the top 53 bits times 2^-53; normals are Box-Muller
 // from the draws i of two consecutive streams.
 //
-// Particle i: x0 = L u_i (positions' stream), x = x0 + amp sin(k x0),
-// wrapped into [0, L); v = v0 (-1)^i for two beams (v0 for one) + vth n_i.
+// Particle i: x0 = L u_i (positions' stream) or the lattice (i + 1/2) L/np,
+// x = x0 + amp sin(k x0) wrapped into [0, L); v = s_i v0 + vth n_i with the
+// beam sign s_i: 1, alternating by index, or + when a uniform of the third
+// velocity stream is below 1/2.
 // Stored as s = x/dx + 1/2 and w = v dt/dx, rounded once to the state
 // precision, exactly as the host conversion does.
 #include <algorithm>
 
+#include "pic.h"
 #include "pic_internal.h"
 
 namespace pic1d {
@@ -35,15 +38,17 @@ __device__ __forceinline__ double uniform53(unsigned long long base, long long i
 
 template <typename T>
 __global__ __launch_bounds__(256) void load_kernel(T *U, T *W, int64_t np, int ng, LoaderArgs a) {
-    const double L = a.L, dx = L / ng, wscale = a.dt / dx;
+    const double L = a.L, dx = L / ng, wscale = a.dt / dx, spacing = L / (double)np;
     const T hi = (T)ng + T(0.5);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
-        const double x0 = L * uniform53(a.base_pos, i);
+        const double x0 = a.lattice ? ((double)i + 0.5) * spacing : L * uniform53(a.base_pos, i);
         double x = a.amp != 0.0 ? x0 + a.amp * sin(a.k * x0) : x0;
         x = x - L * __builtin_floor(x / L);
         if (x >= L) x = 0.0;
-        double v = a.two_beams ? ((i & 1) ? -a.v0 : a.v0) : a.v0;
+        double v = a.v0;
+        if (a.beams == PIC_BEAMS_ALTERNATE && (i & 1)) v = -a.v0;
+        if (a.beams == PIC_BEAMS_RANDOM && !(uniform53(a.base_sign, i) < 0.5)) v = -a.v0;
         if (a.vth != 0.0) {
             const double u1 = uniform53(a.base_v1, i), u2 = uniform53(a.base_v2, i);
             v += a.vth * (sqrt(-2.0 * log1p(-u1)) * cos(6.283185307179586 * u2));

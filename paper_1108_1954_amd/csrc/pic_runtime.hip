@@ -228,7 +228,9 @@ pic_status check_particles(const pic_params *p, const double *x0, const double *
 pic_status check_loader(const pic_params *p, const pic_loader *ld) {
     if (!ld) return fail(PIC_EINVAL, "loader is NULL");
     if (ld->pos_stream < 0 || ld->vel_stream < 0) return fail(PIC_EINVAL, "loader streams must be >= 0");
-    if (ld->two_beams != 0 && ld->two_beams != 1) return fail(PIC_EINVAL, "two_beams must be 0 or 1");
+    if (ld->beams != PIC_BEAMS_ONE && ld->beams != PIC_BEAMS_ALTERNATE && ld->beams != PIC_BEAMS_RANDOM)
+        return fail(PIC_EINVAL, "loader beams must be PIC_BEAMS_ONE, _ALTERNATE or _RANDOM");
+    if (ld->lattice != 0 && ld->lattice != 1) return fail(PIC_EINVAL, "loader lattice must be 0 or 1");
     if (!(std::isfinite(ld->amp) && std::isfinite(ld->k) && std::isfinite(ld->v0) && std::isfinite(ld->vth) &&
           ld->vth >= 0))
         return fail(PIC_EINVAL, "loader amp, k, v0 must be finite and vth finite and >= 0");
@@ -248,7 +250,9 @@ LoaderArgs loader_args(const pic_params *p, const pic_loader *ld) {
     a.base_pos = loader_stream_base(ld->seed, ld->pos_stream);
     a.base_v1 = loader_stream_base(ld->seed, ld->vel_stream);
     a.base_v2 = loader_stream_base(ld->seed, ld->vel_stream + 1);
-    a.two_beams = ld->two_beams;
+    a.base_sign = loader_stream_base(ld->seed, ld->vel_stream + 2);
+    a.beams = ld->beams;
+    a.lattice = ld->lattice;
     return a;
 }
 

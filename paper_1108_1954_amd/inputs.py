@@ -100,6 +100,35 @@ def wrap_positions(x: np.ndarray, L: float) -> np.ndarray:
     return x
 
 
+def lattice(n: int, L: float) -> np.ndarray:
+    """Quiet-start positions (i + 1/2) L / n: with n a multiple of the cell
+    count, n/ng particles at the centres of equal sub-intervals of every
+    cell, the appendix's initial load."""
+    return (np.arange(n) + 0.5) * (L / n)
+
+
+def loaded(L: float, np_: int, seed: int, pos_stream: int = 0, vel_stream: int = 1, amp: float = 0.0,
+           k: float = 0.0, v0: float = 0.0, vth: float = 0.0, beams: int = 0,
+           lattice_start: bool = False) -> Tuple[np.ndarray, np.ndarray]:
+    """The initial state a device-loader description stands for (the
+    pic_loader fields): x0 uniform from `pos_stream` or the lattice,
+    displaced by amp sin(k x0) and wrapped; v = s_i v0 + vth n_i with the
+    beam sign s_i = 1 (beams 0), alternating by index (1), or + when the
+    uniform of stream vel_stream + 2 is below 1/2 (2, the appendix's sign
+    draw); normals from streams vel_stream, vel_stream + 1."""
+    x0 = lattice(np_, L) if lattice_start else L * uniform(seed, pos_stream, np_)
+    x = wrap_positions(x0 + amp * np.sin(k * x0) if amp != 0.0 else x0, L)
+    del x0
+    v = np.full(np_, float(v0))
+    if beams == 1:
+        v[1::2] = -float(v0)
+    elif beams == 2:
+        v[~(uniform(seed, vel_stream + 2, np_) < 0.5)] = -float(v0)
+    if vth != 0.0:
+        v += vth * normal(seed, vel_stream, np_)
+    return x, v
+
+
 @dataclass
 class RunSpec:
     """One simulation run: parameters plus a lazily generated initial state.
@@ -176,7 +205,7 @@ def two_stream_small(seed: int = 1, np_: int = 10_000, nsteps: int = 200) -> Run
         return x, v
     return RunSpec(L=L, ng=64, np_=np_, dt=0.1, nsteps=nsteps, name="two_stream_ng64_np1e4", make=make,
                    loader=dict(seed=seed, pos_stream=0, vel_stream=1, amp=1e-3, k=k, v0=0.2, vth=0.0,
-                               two_beams=True))
+                               beams=1))
 
 
 def warm_two_stream_large(seed: int = 2, np_: int = 1 << 26, ng: int = 4096,
@@ -250,7 +279,7 @@ def warm_maxwellian_large(seed: int = 5, np_: int = 1 << 28, ng: int = 8192,
     return RunSpec(L=L, ng=ng, np_=np_, dt=0.05, nsteps=nsteps,
                    name=f"maxwellian_ng{ng}_np{np_}", make=make,
                    loader=dict(seed=seed, pos_stream=0, vel_stream=1, amp=-(1e-2 / k), k=k, v0=0.0, vth=0.1,
-                               two_beams=False))
+                               beams=0))
 
 
 def quiet_two_stream(L: float = 2.053, ng: int = 64, ppc: int = 64, v0: float = 0.2,
@@ -284,19 +313,40 @@ def paper_weak_scaling(cores: int = 128, seed: int = 6, nsteps: int = 1000) -> R
     """The paper's weak-scaling workload (Sec. 5.2 and the appendix's
     parameters) at the size it reaches on `cores` UPC threads: 64 cells and
     64,000 particles per thread, L = 3.1415 per thread, Maxwellian vth = 0.2
-    with no drift, dt = 0.1, 1000 cycles.  Positions are seeded uniform (the
-    paper's own start is a lattice)."""
+    with no drift, dt = 0.1, 1000 cycles, from the appendix's lattice start
+    (1000 particles per cell)."""
     L = 3.1415 * cores
     ng = 64 * cores
     np_ = 64000 * cores
+    ld = dict(seed=seed, pos_stream=0, vel_stream=1, amp=0.0, k=0.0, v0=0.0, vth=0.2, beams=0, lattice=True)
 
     def make():
-        x = wrap_positions(L * uniform(seed, 0, np_), L)
-        v = 0.2 * normal(seed, 1, np_)
-        return x, v
+        return loaded(L, np_, **_host_loader(ld))
     return RunSpec(L=L, ng=ng, np_=np_, dt=0.1, nsteps=nsteps, name=f"paper_weak_scaling_{cores}", make=make,
-                   loader=dict(seed=seed, pos_stream=0, vel_stream=1, amp=0.0, k=0.0, v0=0.0, vth=0.2,
-                               two_beams=False))
+                   loader=ld)
+
+
+def paper_two_stream(cores: int = 4, seed: int = 8, nsteps: int = 200) -> RunSpec:
+    """The two-stream verification run of Sec. 4 (its phase-space figure was
+    made on four UPC threads) with the appendix's sizes per thread: 64 cells,
+    64,000 particles and L = 3.1415 per thread, lattice start, each particle
+    given +0.2 or -0.2 by a uniform draw, cold beams (the figure shows two
+    lines), dt = 0.1, 200 cycles (t = 20, the figure's late snapshot)."""
+    L = 3.1415 * cores
+    ng = 64 * cores
+    np_ = 64000 * cores
+    ld = dict(seed=seed, pos_stream=0, vel_stream=1, amp=0.0, k=0.0, v0=0.2, vth=0.0, beams=2, lattice=True)
+
+    def make():
+        return loaded(L, np_, **_host_loader(ld))
+    return RunSpec(L=L, ng=ng, np_=np_, dt=0.1, nsteps=nsteps, name=f"paper_two_stream_{cores}", make=make,
+                   loader=ld)
+
+
+def _host_loader(ld: dict) -> dict:
+    d = dict(ld)
+    d["lattice_start"] = bool(d.pop("lattice", False))
+    return d
 
 
 def warm_maxwellian_small(seed: int = 7, waves: int = 2, ng: int = 256, ppc: int = 800, vth: float = 0.1,
@@ -306,10 +356,8 @@ def warm_maxwellian_small(seed: int = 7, waves: int = 2, ng: int = 256, ppc: int
     perturbation alpha cos(k x), seeded Maxwellian velocities."""
     L = waves * 2.0 * math.pi / k
     n = ng * ppc
+    ld = dict(seed=seed, pos_stream=0, vel_stream=1, amp=-(alpha / k), k=k, v0=0.0, vth=vth, beams=0, lattice=True)
 
     def make():
-        x0 = (np.arange(n) + 0.5) * (L / n)
-        x = wrap_positions(x0 - (alpha / k) * np.sin(k * x0), L)
-        v = vth * normal(seed, 1, n)
-        return x, v
-    return RunSpec(L=L, ng=ng, np_=n, dt=dt, nsteps=nsteps, name="warm_maxwellian_small", make=make)
+        return loaded(L, n, **_host_loader(ld))
+    return RunSpec(L=L, ng=ng, np_=n, dt=dt, nsteps=nsteps, name="warm_maxwellian_small", make=make, loader=ld)

@@ -23,6 +23,7 @@ PIC_MAX_NG = 8192
 PIC_HIST_COLS = 4
 PIC_FLAG_NONFINITE, PIC_FLAG_MULTIWRAP, PIC_FLAG_SORT = 1, 2, 4
 PIC_SOLVE_EXACT, PIC_SOLVE_CG_PAPER = 0, 1
+PIC_BEAMS_ONE, PIC_BEAMS_ALTERNATE, PIC_BEAMS_RANDOM = 0, 1, 2
 
 SYMBOLS = (
     "pic_last_error", "pic_version", "pic_footprint", "pic_create", "pic_create_loaded", "pic_sort",
@@ -53,13 +54,13 @@ class pic_diag(C.Structure):
 class pic_loader(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("pos_stream", C.c_int32), ("vel_stream", C.c_int32),
                 ("amp", C.c_double), ("k", C.c_double), ("v0", C.c_double), ("vth", C.c_double),
-                ("two_beams", C.c_int32), ("pad_", C.c_int32)]
+                ("beams", C.c_int32), ("lattice", C.c_int32)]
 
 
 def make_loader(seed: int, pos_stream: int = 0, vel_stream: int = 1, amp: float = 0.0, k: float = 0.0,
-                v0: float = 0.0, vth: float = 0.0, two_beams: bool = False) -> pic_loader:
+                v0: float = 0.0, vth: float = 0.0, beams: int = 0, lattice: bool = False) -> pic_loader:
     return pic_loader(seed=int(seed), pos_stream=int(pos_stream), vel_stream=int(vel_stream), amp=float(amp),
-                      k=float(k), v0=float(v0), vth=float(vth), two_beams=int(bool(two_beams)), pad_=0)
+                      k=float(k), v0=float(v0), vth=float(vth), beams=int(beams), lattice=int(bool(lattice)))
 
 
 class pic_batch_config(C.Structure):

@@ -136,15 +136,15 @@ def test_missing_extension_fails_loudly(tmp_path, monkeypatch):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(vth=-0.1), dict(two_beams=2), dict(pos_stream=-1), dict(v0=float("inf")),
+    dict(vth=-0.1), dict(beams=3), dict(beams=-1), dict(lattice=2), dict(pos_stream=-1), dict(v0=float("inf")),
     dict(v0=300.0), dict(vth=5.0),        # (|v0| + 8.58 vth) dt >= L = 2.053 with dt = 0.1
 ])
 def test_loader_rejects_invalid_parameters(lib, bad):
     """Checked on the host before any device work (runs without a GPU)."""
-    d = dict(seed=1, pos_stream=0, vel_stream=1, amp=1e-3, k=3.0, v0=0.2, vth=0.01, two_beams=True)
+    d = dict(seed=1, pos_stream=0, vel_stream=1, amp=1e-3, k=3.0, v0=0.2, vth=0.01, beams=1, lattice=0)
     d.update(bad)
-    ld = P.pic_loader(**{k: (int(v) if k in ("seed", "pos_stream", "vel_stream", "two_beams") else float(v))
-                         for k, v in d.items()}, pad_=0)
+    ld = P.pic_loader(**{k: (int(v) if k in ("seed", "pos_stream", "vel_stream", "beams", "lattice") else float(v))
+                         for k, v in d.items()})
     with pytest.raises(P.PicError) as e:
         P.pic_create_loaded(good(), ld)
     assert e.value.status == P.PIC_EINVAL

@@ -29,6 +29,8 @@ CASES = {
     "two_stream": lambda: I.two_stream_small(np_=200_000),
     "maxwellian": lambda: I.warm_maxwellian_large(np_=1 << 21, ng=2048),
     "paper_weak_scaling": lambda: I.paper_weak_scaling(cores=4),
+    "paper_two_stream": lambda: I.paper_two_stream(cores=4),
+    "maxwellian_lattice": lambda: I.warm_maxwellian_small(),
 }
 
 
