@@ -224,6 +224,19 @@ pic_status pic_read_raw(pic_run *run, void *u, void *w, int64_t cap);
  * float(E qm dt^2/dx).  Any pointer may be NULL; cap >= ng. */
 pic_status pic_read_grid(pic_run *run, int64_t *S, double *E, float *Ehat, int32_t cap);
 
+/* Phase-space density of the current particles: the (x, v) plane that the
+ * two-stream figure of Sec. 4 plots point by point, binned on the device
+ * into counts[iv * nx + ix] (nv rows of nx uint32 counts, caller-allocated).
+ * From the stored state s = x/dx + 1/2, w = v dt/dx and c = dt/dx, in FP64:
+ *   ix = min(floor((s - 1/2) nx / ng), nx - 1),
+ *   y = (w - vmin c) * (nv / ((vmax - vmin) c)),  iv = floor(y) if 0 <= y < nv;
+ * particles with y outside [0, nv) are counted in *outside (may be NULL).
+ * Every particle is counted once: sum(counts) + outside = np.  Needs
+ * 1 <= nx nv <= 16384 and finite vmin < vmax (else EINVAL).  Synchronises;
+ * allocates 8 + 4 nx nv bytes of device memory for the call. */
+pic_status pic_phase_space(pic_run *run, int32_t nx, int32_t nv, double vmin, double vmax, uint32_t *counts,
+                           int64_t *outside);
+
 /* Synchronise and copy history rows [first, first+count) (PIC_HIST_COLS
  * doubles each).  Rows beyond min(steps taken, history_cap) are EINVAL. */
 pic_status pic_read_history(pic_run *run, int64_t first, int64_t count, double *rows);

@@ -73,6 +73,8 @@ def _bind(L):
     L.ora_deposit_fixed.argtypes = [C.c_int32, C.c_int64, dp, ip]
     L.ora_density_fixed.argtypes = [P, ip, dp]
     L.ora_cell_order.argtypes = [C.c_int32, C.c_int64, dp, ip]
+    L.ora_phase_space.argtypes = [P, C.c_int64, dp, dp, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                  C.c_void_p, C.POINTER(C.c_int64)]
     L.ora_solve.argtypes = [P, dp, dp, C.c_void_p]
     L.ora_cg_paper.argtypes = [P, dp, C.c_int32, dp, dp]
     L.ora_cg_paper.restype = C.c_int32
@@ -131,6 +133,18 @@ def cell_order(ng: int, u) -> np.ndarray:
     perm = np.empty(u.size, dtype=np.int64)
     lib().ora_cell_order(int(ng), int(u.size), u, perm)
     return perm
+
+
+def phase_space(p: Params, u, w, nx: int, nv: int, vmin: float, vmax: float) -> Tuple[np.ndarray, int]:
+    """(x, v) counts as an (nv, nx) image from state-form particles
+    u = x/dx, w = v dt/dx, and the number with v outside [vmin, vmax)."""
+    u, w = _f64(u), _f64(w)
+    assert u.size == w.size
+    counts = np.empty((int(nv), int(nx)), dtype=np.uint32)
+    out = C.c_int64(0)
+    lib().ora_phase_space(C.byref(p), int(u.size), u, w, int(nx), int(nv), float(vmin), float(vmax),
+                          counts.ctypes.data, C.byref(out))
+    return counts, out.value
 
 
 def density_fixed(p: Params, S) -> np.ndarray:

@@ -168,6 +168,40 @@ void ora_cell_order(int32_t ng, int64_t np, const double *u, int64_t *perm)
     free(first);
 }
 
+/* Phase-space counts: the (x, v) plane that the two-stream figure of Sec. 4
+ * plots particle by particle, as an nv x nx image.  Particle (x, v) belongs
+ * to column floor(x nx / L) and row floor((v - vmin) nv / (vmax - vmin)); rows
+ * outside [0, nv) are counted in *outside.  Not a step of the cycle: an
+ * output of it.  The particles come in the engine's state form u = x/dx,
+ * w = v dt/dx, and each bin is decided in FP64 from those values with one
+ * subtraction and one product (the engine decides the same way):
+ * column min(floor(u nx/ng), nx - 1), y = (w - vmin c) (nv / ((vmax - vmin) c)),
+ * c = dt/dx. */
+void ora_phase_space(const ora_params *p, int64_t np, const double *u, const double *w, int32_t nx, int32_t nv,
+                     double vmin, double vmax, uint32_t *counts, int64_t *outside)
+{
+    double c = p->dt / cell_width(p);
+    double xs = (double)nx / (double)p->ng;
+    double w_lo = vmin * c;
+    double w_bin = (double)nv / ((vmax - vmin) * c);
+    int64_t out = 0;
+    for (int64_t b = 0; b < (int64_t)nx * nv; ++b)
+        counts[b] = 0;
+    for (int64_t i = 0; i < np; ++i) {
+        double y = (w[i] - w_lo) * w_bin;
+        if (!(y >= 0.0 && y < (double)nv)) {
+            out += 1;
+            continue;
+        }
+        int64_t col = (int64_t)floor(u[i] * xs);
+        if (col > nx - 1)
+            col = nx - 1;
+        int64_t row = (int64_t)floor(y);
+        counts[row * nx + col] += 1;
+    }
+    *outside = out;
+}
+
 /* Charge density from the fixed-point sums: rho_g = rho0 + (Q/dx) S_g 2^-32. */
 void ora_density_fixed(const ora_params *p, const int64_t *S, double *rho)
 {

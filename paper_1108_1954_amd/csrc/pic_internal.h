@@ -146,6 +146,15 @@ struct LoaderArgs {
     int32_t beams, lattice;
 };
 unsigned long long loader_stream_base(unsigned long long seed, int stream);
+
+// Phase-space binning (pic_phase.hip): bins of (x, v) as described there.
+constexpr int kMaxPhaseBins = 16384;
+struct PhaseArgs {
+    double xs, w_lo, w_bin;
+    int32_t nx, nv;
+};
+hipError_t launch_phase(const void *u, const void *w, int64_t np, int precision, const PhaseArgs &a,
+                        unsigned *counts, unsigned long long *outside, int cus, hipStream_t stream);
 hipError_t launch_loader(void *u, void *w, int64_t np, int ng, int precision, const LoaderArgs &a, int cus,
                          hipStream_t stream);
 

@@ -1,0 +1,63 @@
+// Phase-space density of a run's particles (gfx950): the (x, v) plane of
+// the paper's two-stream figure (Sec. 4), binned on the device so that a
+// snapshot of 10^8 particles leaves the GPU as a small integer image.
+//
+// Bins, from the stored state s = x/dx + 1/2 and w = v dt/dx in FP64:
+//   ix = floor((s - 1/2) xs),  xs = nx / ng, clamped to nx - 1;
+//   y  = (w - w_lo) w_bin,     counted in row iv = floor(y) iff 0 <= y < nv,
+// otherwise in `outside`.  s - 1/2 is exact, and each bin index comes from
+// one subtraction and one product (no contraction), so a host holding the
+// same state and constants finds the same bins.
+#include <algorithm>
+
+#include "pic_internal.h"
+
+namespace pic1d {
+
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void phase_kernel(const T *__restrict__ U, const T *__restrict__ W, int64_t np,
+                                                    PhaseArgs a, unsigned *__restrict__ counts,
+                                                    unsigned long long *__restrict__ outside) {
+#pragma clang fp contract(off)
+    extern __shared__ unsigned hist[];
+    const int nbins = a.nx * a.nv;
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    const double nvf = (double)a.nv;
+    unsigned out = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
+        const double u = (double)U[i] - 0.5;
+        const double y = ((double)W[i] - a.w_lo) * a.w_bin;
+        if (y >= 0.0 && y < nvf) {
+            const int ix = min((int)(u * a.xs), a.nx - 1);
+            atomicAdd(&hist[(int)y * a.nx + ix], 1u);
+        } else {
+            ++out;
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x)
+        if (hist[b]) atomicAdd(&counts[b], hist[b]);
+    for (int off = 32; off > 0; off >>= 1) out += __shfl_xor(out, off);
+    if ((threadIdx.x & 63) == 0 && out) atomicAdd(outside, (unsigned long long)out);
+}
+
+}  // namespace
+
+hipError_t launch_phase(const void *u, const void *w, int64_t np, int precision, const PhaseArgs &a,
+                        unsigned *counts, unsigned long long *outside, int cus, hipStream_t stream) {
+    const int nbins = a.nx * a.nv;
+    if (np < 1 || a.nx < 1 || a.nv < 1 || nbins > kMaxPhaseBins || !u || !w || !counts || !outside)
+        return hipErrorInvalidValue;
+    const int grid = (int)std::min<int64_t>((np + 255) / 256, (int64_t)cus * 8);
+    const size_t lds = (size_t)nbins * sizeof(unsigned);
+    PhaseArgs args_copy = a;
+    void *args[] = {(void *)&u, (void *)&w, (void *)&np, (void *)&args_copy, (void *)&counts, (void *)&outside};
+    const void *fn = precision ? (const void *)phase_kernel<double> : (const void *)phase_kernel<float>;
+    return hipLaunchKernel(fn, dim3(grid), dim3(256), args, lds, stream);
+}
+
+}  // namespace pic1d

@@ -29,7 +29,7 @@ SYMBOLS = (
     "pic_last_error", "pic_version", "pic_footprint", "pic_create", "pic_create_loaded", "pic_sort",
     "pic_step", "pic_step_graph", "pic_batch_admit_loaded",
     "pic_step_profiled", "pic_batch_step_profiled", "pic_diagnostics", "pic_read_particles", "pic_read_raw", "pic_read_grid", "pic_read_history",
-    "pic_destroy", "pic_batch_create", "pic_batch_admit", "pic_batch_step", "pic_batch_poll",
+    "pic_phase_space", "pic_destroy", "pic_batch_create", "pic_batch_admit", "pic_batch_step", "pic_batch_poll",
     "pic_batch_run", "pic_batch_release", "pic_batch_usage", "pic_batch_destroy",
 )
 
@@ -115,6 +115,7 @@ def load(path: str = LIB_PATH):
         "pic_read_raw": [vp, vp, vp, i64],
         "pic_read_grid": [vp, vp, vp, vp, i32],
         "pic_read_history": [vp, i64, i64, vp],
+        "pic_phase_space": [vp, i32, i32, C.c_double, C.c_double, vp, C.POINTER(i64)],
         "pic_destroy": [vp],
         "pic_batch_create": [C.POINTER(pic_batch_config), vp, C.POINTER(vp)],
         "pic_batch_admit": [vp, P, dptr, dptr, i64, C.POINTER(i64)],
@@ -236,6 +237,16 @@ def pic_read_raw(run, np_: int, precision: int = PIC_FP32) -> Tuple[np.ndarray, 
     w = np.empty(np_, dtype=dt)
     _check(load().pic_read_raw(run, u.ctypes.data, w.ctypes.data, int(np_)))
     return u, w
+
+
+def pic_phase_space(run, nx: int, nv: int, vmin: float, vmax: float) -> Tuple[np.ndarray, int]:
+    """Device-binned (x, v) counts as an (nv, nx) uint32 image, and the
+    number of particles with v outside [vmin, vmax)."""
+    counts = np.zeros((int(nv), int(nx)), dtype=np.uint32)
+    out = C.c_int64(0)
+    _check(load().pic_phase_space(run, int(nx), int(nv), float(vmin), float(vmax), counts.ctypes.data,
+                                  C.byref(out)))
+    return counts, out.value
 
 
 def pic_read_grid(run, ng: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
@@ -363,6 +374,9 @@ class Run:
 
     def grid(self):
         return pic_read_grid(self.handle, self.params.ng)
+
+    def phase_space(self, nx: int, nv: int, vmin: float, vmax: float):
+        return pic_phase_space(self.handle, nx, nv, vmin, vmax)
 
     def history(self, first: int = 0, count: Optional[int] = None):
         if count is None:

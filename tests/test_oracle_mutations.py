@@ -39,6 +39,11 @@ MUTANTS = [
      "for (int64_t i = np - 1; i >= 0; --i)\n        perm["),
     ("literal cycle kicks with the wrong sign", "            v[i] = v[i] + p->qm * Ep[i] * p->dt;",
      "            v[i] = v[i] - p->qm * Ep[i] * p->dt;"),
+    ("phase image transposed", "counts[row * nx + col] += 1;", "counts[col * nv + row] += 1;"),
+    ("phase velocity offset sign", "double y = (w[i] - w_lo) * w_bin;", "double y = (w[i] + w_lo) * w_bin;"),
+    ("phase column scale", "double xs = (double)nx / (double)p->ng;", "double xs = (double)nv / (double)p->ng;"),
+    ("phase lower velocity edge excluded", "if (!(y >= 0.0 && y < (double)nv)) {",
+     "if (!(y > 0.0 && y < (double)nv)) {"),
 ]
 
 # The pins run against every build (argument lists for the parametrised ones).
@@ -46,6 +51,8 @@ PINS = [
     (T.test_plain_deposit_matches_triangle_bruteforce, [(2,), (4,), (8,)]),
     (T.test_fixed_deposit_total_is_exact_and_matches_bruteforce, [(3,), (8,)]),
     (T.test_fixed_deposit_hand_derived_golden_cases, [()]),
+    (T.test_phase_space_matches_bruteforce, [(8, 5), (3, 7)]),
+    (T.test_phase_space_edges, [()]),
     (T.test_cell_order_hand_derived_case, [()]),
     (T.test_cell_order_is_a_stable_sort_by_nearest_node, [(5,), (64,)]),
     (T.test_fixed_density_matches_plain_density, [()]),

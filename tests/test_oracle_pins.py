@@ -463,3 +463,72 @@ def test_warm_plasma_oscillates_at_the_bohm_gross_frequency():
     w_lf = 2 / s.dt * math.asin(w_bg * s.dt / 2)
     assert len(peaks) >= 5
     assert abs(omega / w_lf - 1) < 2e-3, (omega, w_lf)
+
+
+def phase_bruteforce(L, nx, nv, vmin, vmax, x, v):
+    """Brute force in physical units with exact rational arithmetic: column
+    floor(x nx / L), row floor((v - vmin) nv / (vmax - vmin)), rows outside
+    [0, nv) counted apart."""
+    from fractions import Fraction as Fr
+    counts = np.zeros((nv, nx), dtype=np.int64)
+    out = 0
+    for xi, vi in zip(x, v):
+        row = math.floor((Fr(vi) - Fr(vmin)) * nv / (Fr(vmax) - Fr(vmin)))
+        if not 0 <= row < nv:
+            out += 1
+            continue
+        counts[row, min(math.floor(Fr(xi) * nx / Fr(L)), nx - 1)] += 1
+    return counts, out
+
+
+@pytest.mark.parametrize("nx,nv", [(8, 5), (3, 7)])
+def test_phase_space_matches_bruteforce(nx, nv):
+    """Points well inside their bins (a quarter bin from every edge, where
+    rounding of the state form cannot move them) and outside the velocity
+    range on both sides; columns and rows have different counts so a
+    transposed image fails."""
+    rng = np.random.default_rng(nx * 10 + nv)
+    L, ng, dt, vmin, vmax = 2.5, 16, 0.1, -0.4, 0.6
+    n = 400
+    ix = rng.integers(0, nx, n)
+    iv = rng.integers(-1, nv + 1, n)                  # rows -1 and nv lie outside
+    x = (ix + rng.uniform(0.25, 0.75, n)) * (L / nx)
+    v = vmin + (iv + rng.uniform(0.25, 0.75, n)) * ((vmax - vmin) / nv)
+    p = O.params(L, ng, n, dt=dt)
+    dx = L / ng
+    counts, out = O.phase_space(p, x / dx, v * dt / dx, nx, nv, vmin, vmax)
+    ref, ref_out = phase_bruteforce(L, nx, nv, vmin, vmax, x, v)
+    np.testing.assert_array_equal(counts, ref)
+    assert out == ref_out == int(np.sum((iv < 0) | (iv >= nv)))
+    assert int(counts.sum()) + out == n
+
+
+def test_phase_space_edges():
+    """x = 0 is column 0 and positions just below L the last column; v = vmin
+    is row 0 and v = vmax is outside."""
+    L, ng, dt, nx, nv, vmin, vmax = 4.0, 8, 0.5, 4, 2, -1.0, 1.0
+    dx = L / ng
+    x = np.array([0.0, L * (1 - 1e-15), 1.0, 3.0, 2.0])
+    v = np.array([vmin, 0.0, vmax, -1.5, 0.999])
+    p = O.params(L, ng, x.size, dt=dt)
+    counts, out = O.phase_space(p, x / dx, v * dt / dx, nx, nv, vmin, vmax)
+    ref = np.zeros((nv, nx), dtype=np.uint32)
+    ref[0, 0] = 1                                       # (0, vmin)
+    ref[1, nx - 1] = 1                                  # (L-, 0)
+    ref[1, 2] = 1                                       # (2.0, 0.999)
+    np.testing.assert_array_equal(counts, ref)
+    assert out == 2                                     # v = vmax, v < vmin
+
+
+def test_phase_space_of_a_two_stream_load_has_two_lines():
+    """The cold two-stream load of Sec. 4 occupies exactly the two velocity
+    rows of +-v0, uniformly in x (lattice positions)."""
+    spec = I.paper_two_stream(cores=1)
+    x, v = spec.particles()
+    dx = spec.L / spec.ng
+    p = O.params(spec.L, spec.ng, spec.np_, dt=spec.dt)
+    counts, out = O.phase_space(p, x / dx, v * spec.dt / dx, 64, 40, -0.51, 0.49)
+    assert out == 0
+    rows = np.flatnonzero(counts.sum(axis=1))
+    assert list(rows) == [12, 28]                       # floor((+-0.2 + 0.51) * 40), away from edges
+    assert np.all(counts[rows].sum(axis=0) == spec.np_ // 64)
