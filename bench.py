@@ -106,7 +106,18 @@ def cpu_baseline(spec, parts, budget_s=15.0):
     dt = time.perf_counter() - t
     return {"value": spec.np_ * n / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"FP64 oracle (fixed-point deposit), one ensemble run np={spec.np_} ng={spec.ng}, "
-                      f"{n} steps, {dt:.1f} s, single thread"}
+                      f"{n} steps, {dt:.1f} s, single thread",
+            "cpu": cpu_model(), "host_cores": os.cpu_count()}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 COPY_BYTES = 1 << 30
