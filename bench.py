@@ -258,7 +258,7 @@ def main():
         sp = I.paper_weak_scaling(cores=128)
         paper = {"workload": f"the paper's weak-scaling run at its 128-thread size on one GPU: ng={sp.ng}, "
                              f"np={sp.np_}, L={sp.L:.1f}, Maxwellian vth=0.2, dt=0.1, {sp.nsteps} cycles; "
-                             "particles drawn on the device (pic_create_loaded)"}
+                             "lattice start, particles drawn on the device (pic_create_loaded)"}
         for label, solver in (("exact_solve", P.PIC_SOLVE_EXACT), ("paper_cg_150", P.PIC_SOLVE_CG_PAPER)):
             pp = P.make_params(sp.L, sp.ng, sp.np_, sp.dt, solver=solver, cg_iters=150)
             rp = P.Run(pp, loader=P.make_loader(**sp.loader))
