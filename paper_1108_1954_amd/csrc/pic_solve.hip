@@ -287,7 +287,14 @@ __device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, int 
 // The face field F_{g+1/2} = -(phi_{g+1} - phi_g)/dx satisfies
 // F_{g+1/2} - F_{g-1/2} = (rho_g - mean rho) dx, so it is a prefix sum;
 // periodicity of phi sets sum_g F_{g+1/2} = 0; the central-difference node
-// field is E_g = (F_{g-1/2} + F_{g+1/2}) / 2.  D: LDS scratch of ng doubles.
+// field is E_g = (F_{g-1/2} + F_{g+1/2}) / 2.  D: LDS scratch of
+// kSolveLds doubles.  The exact solve runs a serial prefix sum over each
+// thread's contiguous segment of nodes, so it stores node g at dpad(g) (one
+// spare slot after every 8 nodes): the threads of a wavefront then hit
+// distinct LDS banks instead of a few.  The CG indexes D by node.
+constexpr int kSolveLds = kMaxNg + kMaxNg / 8;
+__device__ __forceinline__ int dpad(int g) { return g + (g >> 3); }
+
 __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, long long *redi,
                                        bool prologue) {
     const int ng = R->ng;
@@ -304,6 +311,7 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
     // sums keep the strided order g = tid, tid + 256, ...
     constexpr int kBatch = 16;
     long long tot = 0;
+    const bool cg = R->solver == 1;
     if (worker) {
         for (int g0 = tid; g0 < ng; g0 += nthr * kBatch) {
             unsigned long long sv[kBatch];
@@ -319,7 +327,7 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
                     S[g] = 0ull;
                     S_last[g] = sv[k];
                     tot += (long long)sv[k];
-                    D[g] = (double)sv[k];
+                    D[cg ? g : dpad(g)] = (double)sv[k];
                 }
             }
         }
@@ -346,7 +354,6 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
     }
     tot = solve_sum(tot, redi, pari, nthr);                   // exact: sum_g S_g
     const double meanS = (double)tot / (double)ng;
-    const bool cg = R->solver == 1;
     double C = 0.0;
     if (cg) {
         __syncthreads();                          // D holds every S_g
@@ -357,14 +364,14 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
         const int g0 = worker ? min(tid * seg, ng) : ng, g1 = min(g0 + seg, ng);
         double acc = 0.0;
         for (int g = g0; g < g1; ++g) {
-            acc += (D[g] - meanS) * scale;
-            D[g] = acc;
+            acc += (D[dpad(g)] - meanS) * scale;
+            D[dpad(g)] = acc;
         }
         const double off = solve_exclusive_scan(acc, red, par, nthr);
         double csum = 0.0;
         for (int g = g0; g < g1; ++g) {
-            double fv = D[g] + off;
-            D[g] = fv;
+            double fv = D[dpad(g)] + off;
+            D[dpad(g)] = fv;
             csum += fv;
         }
         C = -solve_sum(csum, red, par, nthr) / (double)ng;   // syncs: D complete
@@ -380,8 +387,8 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
             if (cg) {
                 E = D[g];
             } else {
-                double left = D[g == 0 ? ng - 1 : g - 1];
-                E = 0.5 * (left + D[g]) + C;
+                double left = D[dpad(g == 0 ? ng - 1 : g - 1)];
+                E = 0.5 * (left + D[dpad(g)]) + C;
             }
             E64[g] = E;
             double eh = E * ecoef;
@@ -417,7 +424,7 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
 // Second launch of a step: workgroup b solves run runs[b] for E^{n+1} and
 // records the diagnostics; runs that are idle or finished return at once.
 __global__ __launch_bounds__(kMaxSolveThreads) void solve_kernel(RunDev *runs, int prologue) {
-    __shared__ double D[kMaxNg];
+    __shared__ double D[kSolveLds];
     __shared__ double red[2 * kRedSlots];
     __shared__ long long redi[2 * kRedSlots];
     RunDev *R = runs + blockIdx.x;
