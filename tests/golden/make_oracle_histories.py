@@ -6,7 +6,7 @@ paper_1108_1954_amd.inputs and stores, per step n, the oracle's
 engine's field-energy history with these files.
 
     python tests/golden/make_oracle_histories.py warm_two_stream   # ~20 min, one core
-    python tests/golden/make_oracle_histories.py maxwellian        # ~2 h, one core
+    python tests/golden/make_oracle_histories.py maxwellian        # ~4 h, one core
 """
 import os
 import sys

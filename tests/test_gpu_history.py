@@ -185,3 +185,71 @@ def test_full_ensemble_in_the_bench_configuration():
               f"sampled runs {sample} checked", flush=True)
     finally:
         P.pic_batch_destroy(b)
+
+
+def check_full_size_run(spec, p, r, sample=200_000, cg_iters=0):
+    """After steps in the benchmark's configuration: the deposit of the
+    downloaded state is bit-exact, the field equals the oracle's solve of it
+    (exact solve, or the paper's CG with the same iteration count) within
+    its bound, and one more step of a sample of particles matches the
+    oracle's gather and push within the rounding bound."""
+    import test_gpu_parity as G
+    import test_gpu_cg as CG
+    from oracle import oracle as O
+    u0, w0 = r.raw()
+    S0, E0, Eh0 = r.grid()
+    np.testing.assert_array_equal(S0, O.deposit_fixed(spec.ng, u0.astype(np.float64)))
+    assert int(S0.sum()) == spec.np_ << 32
+    op = G.oracle_params(p)
+    rho = O.density_fixed(op, S0)
+    if cg_iters:
+        _, E_ora, _ = O.cg_paper(op, rho, maxit=cg_iters)
+        spread = np.abs(CG.cg_numpy(rho, spec.L / spec.ng, cg_iters) - E_ora).max()
+        tol = 10 * spread + 16 * spec.ng * G.EPS64 * np.abs(E_ora).max()
+    else:
+        E_ora, _ = O.solve(op, rho)
+        tol = G.solve_tolerance(p, S0)
+    assert np.abs(E0 - E_ora).max() <= tol
+    pick = np.random.default_rng(1).choice(spec.np_, size=min(spec.np_, sample), replace=False)
+    r.step(1, graph_steps=0)
+    u1, w1 = r.raw()
+    dx = spec.L / spec.ng
+    ops = O.params(spec.L, spec.ng, pick.size, dt=spec.dt)
+    x0 = u0[pick].astype(np.float64) * dx
+    v0 = w0[pick].astype(np.float64) * dx / spec.dt
+    x1, v1, _ = O.push(ops, x0, v0, O.gather(ops, x0, E_ora))
+    du, dw = G.push_tolerance(x1 / dx, v1 * spec.dt / dx, np.abs(Eh0).max(), spec.ng, G.EPS32)
+    assert np.all(np.abs(w1[pick].astype(np.float64) - v1 * spec.dt / dx) <= dw)
+    assert np.all(np.abs(G.periodic_diff(u1[pick], x1 / dx, spec.ng)) <= du)
+    S1, _, _ = r.grid()
+    np.testing.assert_array_equal(S1, O.deposit_fixed(spec.ng, u1.astype(np.float64)))
+
+
+def test_single_large_run_in_the_bench_configuration():
+    """The warm two-stream run at full size (2^26 particles, ng 4096) as the
+    benchmark's single-run line times it: autotuned shape, graph replay."""
+    spec = I.warm_two_stream_large()
+    print(f"full-size single run np={spec.np_} ng={spec.ng}", flush=True)
+    x, v = spec.particles()
+    p = P.make_params(spec.L, spec.ng, spec.np_, spec.dt)
+    with P.Run(p, x, v) as r:
+        del x, v
+        r.step(20, graph_steps=20)
+        d, _, _ = r.diagnostics()
+        assert d["step"] == 20 and d["flags"] == 0
+        check_full_size_run(spec, p, r)
+
+
+@pytest.mark.parametrize("solver", [P.PIC_SOLVE_EXACT, P.PIC_SOLVE_CG_PAPER])
+def test_paper_workload_in_the_bench_configuration(solver):
+    """The paper's weak-scaling workload at its 128-thread size (ng 8192,
+    8.192M particles, lattice start drawn on the device), with the exact
+    solve and with the paper's 150-iteration CG."""
+    spec = I.paper_weak_scaling(cores=128)
+    print(f"paper workload np={spec.np_} ng={spec.ng} solver={solver}", flush=True)
+    p = P.make_params(spec.L, spec.ng, spec.np_, spec.dt, solver=solver, cg_iters=150)
+    with P.Run(p, loader=P.make_loader(**spec.loader)) as r:
+        r.step(20, graph_steps=20)
+        d, _, _ = r.diagnostics()
+        assert d["step"] == 20 and d["flags"] == 0
+        check_full_size_run(spec, p, r, cg_iters=150 if solver == P.PIC_SOLVE_CG_PAPER else 0)
