@@ -159,8 +159,9 @@ pic_status pic_create(const pic_params *params, const double *x0, const double *
  * sin/log1p/cos may differ from a host library's in the last bit. */
 typedef struct pic_loader {
     uint64_t seed;
-    int32_t  pos_stream;   /* stream of the position uniforms              */
-    int32_t  vel_stream;   /* first of the two streams of the normals      */
+    int32_t  pos_stream;   /* stream of the position uniforms, 0..2^30     */
+    int32_t  vel_stream;   /* first of the streams of the normals (then the
+                              beam signs at vel_stream + 2), 0..2^30         */
     double   amp;          /* displacement amplitude (length)              */
     double   k;            /* its wavenumber                               */
     double   v0;           /* drift speed                                  */

@@ -85,18 +85,16 @@ DeviceInfo device_info() {
     return d;
 }
 
-bool finite_pos(double v) { return std::isfinite(v); }
-
 pic_status validate(const pic_params *p) {
     if (!p) return fail(PIC_EINVAL, "params is NULL");
-    if (!(finite_pos(p->L) && p->L > 0)) return fail(PIC_EINVAL, "L must be finite and > 0 (got %g)", p->L);
+    if (!(std::isfinite(p->L) && p->L > 0)) return fail(PIC_EINVAL, "L must be finite and > 0 (got %g)", p->L);
     if (p->ng < 2 || p->ng > PIC_MAX_NG)
         return fail(PIC_EINVAL, "ng must be in [2, %d] (got %d)", PIC_MAX_NG, p->ng);
     if (p->np < 1 || p->np >= (int64_t)1 << 31)
         return fail(PIC_EINVAL, "np must be in [1, 2^31) (got %lld)", (long long)p->np);
-    if (!(finite_pos(p->dt) && p->dt > 0)) return fail(PIC_EINVAL, "dt must be finite and > 0");
+    if (!(std::isfinite(p->dt) && p->dt > 0)) return fail(PIC_EINVAL, "dt must be finite and > 0");
     if (!(std::isfinite(p->qm) && p->qm != 0)) return fail(PIC_EINVAL, "qm must be finite and nonzero");
-    if (!(finite_pos(p->rho0) && p->rho0 > 0)) return fail(PIC_EINVAL, "rho0 must be finite and > 0");
+    if (!(std::isfinite(p->rho0) && p->rho0 > 0)) return fail(PIC_EINVAL, "rho0 must be finite and > 0");
     if (p->precision != PIC_FP32 && p->precision != PIC_FP64)
         return fail(PIC_EINVAL, "precision must be PIC_FP32 or PIC_FP64");
     if (p->tile < 0 || p->tile % kUnit != 0 || p->tile > (1 << 20))
@@ -108,15 +106,13 @@ pic_status validate(const pic_params *p) {
     return PIC_OK;
 }
 
-// Particles per tile: a pure function of np, so that every launch shape and
-// schedule sees the same tiles (and the same diagnostic summation order).
-// At least 1024 (a full vector block for every unroll), at most 16384, and
-// about np/1024 otherwise so that large runs give every wavefront a tile.
-// Default tile (a function of np only, so a run is tiled alike everywhere):
-// about 4096 tiles per run, so that a large single run gives the device's
-// wavefronts a tile each (one tile per wavefront at a time); at least 2048
-// particles from 1M particles on (fewer per-tile start-ups when many runs
-// share the device), at least 1024 and at most 16384 (whole block units).
+// Default particles per tile: a pure function of np, so that every launch
+// shape and schedule sees the same tiles (and the same diagnostic summation
+// order).  About 4096 tiles per run, so that a large single run gives the
+// device's wavefronts a tile each (one tile per wavefront at a time); at
+// least 2048 particles from 1M particles on (fewer per-tile start-ups when
+// many runs share the device), at least 1024 and at most 16384 (whole block
+// units).
 int default_tile(int64_t np) {
     const int64_t per = (np + 4095) / 4096;
     int64_t t = (per + kUnit - 1) / kUnit * kUnit;
@@ -227,7 +223,8 @@ pic_status check_particles(const pic_params *p, const double *x0, const double *
 // the single-wrap contract |v| dt < L is checked on that bound.
 pic_status check_loader(const pic_params *p, const pic_loader *ld) {
     if (!ld) return fail(PIC_EINVAL, "loader is NULL");
-    if (ld->pos_stream < 0 || ld->vel_stream < 0) return fail(PIC_EINVAL, "loader streams must be >= 0");
+    if (ld->pos_stream < 0 || ld->vel_stream < 0 || ld->pos_stream > (1 << 30) || ld->vel_stream > (1 << 30))
+        return fail(PIC_EINVAL, "loader streams must be in [0, 2^30]");
     if (ld->beams != PIC_BEAMS_ONE && ld->beams != PIC_BEAMS_ALTERNATE && ld->beams != PIC_BEAMS_RANDOM)
         return fail(PIC_EINVAL, "loader beams must be PIC_BEAMS_ONE, _ALTERNATE or _RANDOM");
     if (ld->lattice != 0 && ld->lattice != 1) return fail(PIC_EINVAL, "loader lattice must be 0 or 1");

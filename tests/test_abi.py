@@ -136,7 +136,8 @@ def test_missing_extension_fails_loudly(tmp_path, monkeypatch):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(vth=-0.1), dict(beams=3), dict(beams=-1), dict(lattice=2), dict(pos_stream=-1), dict(v0=float("inf")),
+    dict(vth=-0.1), dict(beams=3), dict(beams=-1), dict(lattice=2), dict(pos_stream=-1), dict(vel_stream=2**31 - 1),
+    dict(v0=float("inf")),
     dict(v0=300.0), dict(vth=5.0),        # (|v0| + 8.58 vth) dt >= L = 2.053 with dt = 0.1
 ])
 def test_loader_rejects_invalid_parameters(lib, bad):
