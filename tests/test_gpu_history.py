@@ -8,8 +8,8 @@
     whole-run error is reported as a number, not held to a bound.
   * Warm Maxwellian (np = 2^28, ng = 8192, 2000 steps): the Langmuir
     oscillation of the loaded k = 0.5 mode must have the Bohm-Gross frequency
-    with the leapfrog correction; with the stored oracle history, the FP32
-    and FP64-state paths are both compared with it.
+    with the leapfrog correction, and the FP32 and FP64-state histories are
+    compared with the stored FP64 oracle history.
   * The batched ensemble (256 runs, ~1.45e8 particles) in the launch
     configuration the benchmark times: exact charge for every run, sampled
     runs' deposits bit-exact, fields and one step within the rounding bounds.
@@ -115,15 +115,16 @@ def test_warm_maxwellian_langmuir_frequency_and_precision():
         w = oscillation_frequency(h[:, 1], dt)
         print(f"{name} state: Langmuir frequency {w:.5f} (Bohm-Gross with leapfrog {w_lf:.5f})", flush=True)
         assert abs(w / w_lf - 1) < 2e-3
-    path = os.path.join(GOLDEN, "oracle_history_maxwellian.txt")
-    if os.path.exists(path):
-        ref = np.loadtxt(path)
-        e32 = float(np.max(np.abs(h32[:, 1] - ref[:, 1])) / ref[:, 1].max())
-        e64 = float(np.max(np.abs(h64[:, 1] - ref[:, 1])) / ref[:, 1].max())
-        print(f"W_E history vs FP64 oracle over {spec.nsteps} steps: FP32 state {e32:.3e}, "
-              f"FP64 state {e64:.3e}", flush=True)
-        assert e64 <= e32
-        assert e32 < 1e-2
+    ref = golden("maxwellian")
+    e32 = float(np.max(np.abs(h32[:, 1] - ref[:, 1])) / ref[:, 1].max())
+    e64 = float(np.max(np.abs(h64[:, 1] - ref[:, 1])) / ref[:, 1].max())
+    print(f"W_E history vs FP64 oracle over {spec.nsteps} steps: FP32 state {e32:.3e}, "
+          f"FP64 state {e64:.3e}", flush=True)
+    # A stable plasma: rounding differences do not grow exponentially as in
+    # the two-stream run.  Measured 4.2e-7 (FP32 state) and 3.1e-13 (FP64).
+    assert e64 <= e32
+    assert e32 < 1e-4
+    assert e64 < 1e-9
 
 
 def test_full_ensemble_in_the_bench_configuration():
