@@ -111,41 +111,15 @@ __device__ __forceinline__ void push(T &s, T &w, T Ep, T ngf, T hi, uint32_t &fl
     s = sn;
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-// Add every lane's pair (2^32 - F at node j, F at node j + 1) to the LDS
-// grid.  When all 64 lanes have their left node at j0 or j0 + 1 (j0 the
-// first lane's; typical once particles are in cell order), the pairs are
-// summed across the wavefront first and one lane adds the node totals, so
-// 64 lanes do not serialise on the same LDS addresses.  Integer sums: the
-// grid gets exactly the same values either way.
+// Add the lane's pair (2^32 - F at node j, F at node j + 1) to the LDS
+// grid.  Plain LDS atomics also when many lanes share a node (cell-ordered
+// particles, quiet starts): on gfx950 a wavefront's same-address LDS
+// atomics cost about as much as a wavefront pre-reduction, measured on
+// sorted and unsorted runs, so the pass keeps the shorter code.
 __device__ __forceinline__ void deposit_pair(int j, uint32_t F, unsigned long long *Sl) {
-    const int j0 = __builtin_amdgcn_readfirstlane(j);
-    const bool up = j == j0 + 1;
-    const unsigned long long act = __ballot(1);
-    if (act == ~0ull && __ballot(j == j0 || up) == act) {
-        const uint32_t F0 = up ? 0u : F, F1 = up ? F : 0u;
-        // 16-bit halves keep the 32-bit wavefront sums exact
-        const uint32_t s0lo = wave_sum_u32(F0 & 0xffffu), s0hi = wave_sum_u32(F0 >> 16);
-        const uint32_t s1lo = wave_sum_u32(F1 & 0xffffu), s1hi = wave_sum_u32(F1 >> 16);
-        const unsigned long long n1 = (unsigned long long)__popcll(__ballot(up));
-        if ((threadIdx.x & 63) == 0) {
-            const unsigned long long S0 = ((unsigned long long)s0hi << 16) + s0lo;
-            const unsigned long long S1 = ((unsigned long long)s1hi << 16) + s1lo;
-            unsigned long long *p = Sl + (j0 + 1);
-            atomicAdd(p, ((64ull - n1) << 32) - S0);
-            atomicAdd(p + 1, S0 + (n1 << 32) - S1);
-            if (n1) atomicAdd(p + 2, S1);          // only then is j0 + 1 a real left node
-        }
-    } else {
-        unsigned long long *p = Sl + (j + 1);
-        atomicAdd(p, (1ull << 32) - (unsigned long long)F);
-        atomicAdd(p + 1, (unsigned long long)F);
-    }
+    unsigned long long *p = Sl + (j + 1);
+    atomicAdd(p, (1ull << 32) - (unsigned long long)F);
+    atomicAdd(p + 1, (unsigned long long)F);
 }
 
 // Exact fixed-point charge deposit (Sec. 2.3 weights): with
