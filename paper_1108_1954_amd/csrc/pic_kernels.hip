@@ -228,9 +228,9 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
     constexpr int SPB = kUnit / PER;                 // sub-blocks per block unit
     static_assert(kUnit % PER == 0, "a block unit holds whole sub-blocks");
     // Register sets in the load pipeline: three at one vector per lane
-    // (87 VGPRs, five waves per SIMD), two when the sub-blocks are wider
-    // (a third would spill at 1024 threads).  Four sets at one vector cost
-    // a wave per SIMD and measured slower.
+    // (84 VGPRs, five waves per SIMD), two when the sub-blocks are wider
+    // (a third measured no faster and spills at 1024 threads).  Four sets
+    // at one vector cost a wave per SIMD and measured slower.
     constexpr int DEPTH = UNROLL == 1 ? 3 : 2;
     const int ng = R->ng;
     const int64_t np = R->np;
