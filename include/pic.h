@@ -66,7 +66,8 @@ typedef enum { PIC_FP32 = 0, PIC_FP64 = 1 } pic_precision;
 /* Run parameters (Appendix A lists the paper's: L, ng, np, dt, qm, rho0).
  * Validation: ng in [2, PIC_MAX_NG]; 1 <= np < 2^31; L > 0; dt > 0;
  * qm != 0; rho0 > 0; all finite; precision PIC_FP32 or PIC_FP64;
- * solver PIC_SOLVE_EXACT or PIC_SOLVE_CG_PAPER; 0 <= cg_iters <= 100000. */
+ * solver PIC_SOLVE_EXACT or PIC_SOLVE_CG_PAPER; 0 <= cg_iters <= 100000;
+ * sort_every >= PIC_SORT_AUTO. */
 typedef struct pic_params {
     double  L;            /* periodic domain length                          */
     int32_t ng;           /* cells = grid nodes                              */
@@ -75,7 +76,8 @@ typedef struct pic_params {
     double  dt;           /* time step                                       */
     double  qm;           /* charge-to-mass ratio (electrons: -1)            */
     double  rho0;         /* ion background density (paper: 1)              */
-    int32_t sort_every;   /* cell sort every K > 0 steps; <= 0 never (no room reserved) */
+    int32_t sort_every;   /* cell sort every K > 0 steps; 0 never (no room
+                             reserved); PIC_SORT_AUTO: K chosen at creation */
     int32_t tile;         /* particles per tile (multiple of 1024); 0 = default */
     int64_t history_cap;  /* per-step history rows kept on the device        */
     int32_t solver;       /* PIC_SOLVE_EXACT (default) or PIC_SOLVE_CG_PAPER   */
@@ -182,6 +184,20 @@ enum {
 pic_status pic_create_loaded(const pic_params *params, const pic_loader *loader, void *dev_mem,
                              size_t dev_bytes, void *stream, pic_run **out);
 
+/* sort_every = PIC_SORT_AUTO (single runs only): at creation the engine
+ * times the particle pass on the loaded state, the cell sort, and the pass
+ * on the sorted state (HIP events, on a saved copy of the state that is put
+ * back, so the run's results are as without the trial), and sorts every
+ * K = ceil(2 t_sort / (t_unsorted - t_sorted)) steps if sorting makes the
+ * pass faster, else never.  Room for the sort is reserved either way.
+ * The storage order, and with it the rounding of the FP64 kinetic-energy
+ * and momentum sums, then depends on the K chosen; particle values and the
+ * deposit do not.  pic_sort_period reports K. */
+#define PIC_SORT_AUTO (-1)
+
+/* The run's cell-sort period after creation: K > 0, or 0 for never. */
+pic_status pic_sort_period(pic_run *run, int32_t *k);
+
 /* Enqueue `nsteps` >= 0 steps (asynchronous; returns before they run).
  * With sort_every = K > 0, the particles are reordered by cell (pic_sort)
  * before steps K+1, 2K+1, ... counted from creation. */
@@ -192,7 +208,7 @@ pic_status pic_step(pic_run *run, int64_t nsteps);
  * also runs every sort_every steps.  Positions, velocities and every later
  * result are unchanged as a multiset; only the storage order changes (and
  * with it the per-tile summation order of the kinetic-energy and momentum
- * diagnostics).  PIC_ESTATE if the run was created with sort_every <= 0
+ * diagnostics).  PIC_ESTATE if the run was created with sort_every = 0
  * (no room for the sort's alternate arrays). */
 pic_status pic_sort(pic_run *run);
 
@@ -268,7 +284,7 @@ typedef struct pic_batch_config {
 pic_status pic_batch_create(const pic_batch_config *cfg, void *stream, pic_batch **out);
 
 /* Admit a run that will take `nsteps` steps from host x0[np], v_mhalf[np]
- * (as pic_create; FP32 state only, ng <= ng_max).  PIC_EBUDGET if its
+ * (as pic_create; FP32 state only, ng <= ng_max, sort_every >= 0).  PIC_EBUDGET if its
  * footprint does not fit the arena or the run table is full now (nothing is
  * changed; retry after releases).  Asynchronous: the particles are converted
  * into pinned staging memory before the call returns (the caller's arrays

@@ -103,6 +103,8 @@ pic_status validate(const pic_params *p) {
     if (p->solver != PIC_SOLVE_EXACT && p->solver != PIC_SOLVE_CG_PAPER)
         return fail(PIC_EINVAL, "solver must be PIC_SOLVE_EXACT or PIC_SOLVE_CG_PAPER (got %d)", p->solver);
     if (p->cg_iters < 0 || p->cg_iters > 100000) return fail(PIC_EINVAL, "cg_iters must be in [0, 100000]");
+    if (p->sort_every < PIC_SORT_AUTO)
+        return fail(PIC_EINVAL, "sort_every must be >= 0 or PIC_SORT_AUTO (got %d)", p->sort_every);
     return PIC_OK;
 }
 
@@ -143,7 +145,7 @@ Layout make_layout(const pic_params *p) {
     };
     L.u = take(np_pad * L.esize);
     L.w = take(np_pad * L.esize);
-    L.sorting = p->sort_every > 0;
+    L.sorting = p->sort_every > 0 || p->sort_every == PIC_SORT_AUTO;
     if (L.sorting) {
         L.u_alt = take(np_pad * L.esize);
         L.w_alt = take(np_pad * L.esize);
@@ -189,7 +191,7 @@ struct pic_run {
     bool swapped = false;
     void *cur_u() const { return swapped ? host.u_alt : host.u; }
     void *cur_w() const { return swapped ? host.w_alt : host.w; }
-    int sort_every() const { return lay.sorting ? p.sort_every : 0; }
+    int sort_every() const { return lay.sorting && p.sort_every > 0 ? p.sort_every : 0; }
     // graph replay cache
     hipGraphExec_t graph = nullptr;       // graph_steps steps
     hipGraphExec_t graph_sort = nullptr;  // cell sort + graph_steps steps
@@ -428,6 +430,71 @@ pic_status choose_shape(pic_run *r, const DeviceInfo &d) {
     return PIC_OK;
 }
 
+// Cell-sort period of a run created with PIC_SORT_AUTO: the particle pass
+// timed on the state as loaded, the sort, and the pass on the sorted state
+// (kReps passes each, HIP events on the run's stream), all on a saved copy
+// of the state that is put back afterwards.  Sort every
+// K = ceil(2 t_sort / (t_unsorted - t_sorted)) steps (twice the steps the
+// sort takes to pay for itself) if sorting makes the pass faster, else never.
+pic_status choose_sort_period(pic_run *r) {
+    constexpr int kReps = 3;
+    char *tmp = nullptr;
+    const size_t bytes = 2 * (size_t)r->p.np * r->lay.esize;
+    if (hipMalloc((void **)&tmp, bytes) != hipSuccess)
+        return fail(PIC_ENOMEM, "sort-period trial scratch of %zu bytes", bytes);
+    hipEvent_t ev[4] = {};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    pic_status st = e == hipSuccess ? save_particles(r, tmp, false) : PIC_OK;
+    auto pass = [r]() {
+        return launch_particles(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng, r->p.precision, 0,
+                                r->stream);
+    };
+    float t_u = 0, t_sort = 0, t_s = 0;
+    if (e == hipSuccess && st == PIC_OK) {
+        e = pass();                                                      // warm-up
+        if (e == hipSuccess) e = hipEventRecord(ev[0], r->stream);
+        for (int k = 0; k < kReps && e == hipSuccess; ++k) e = pass();
+        if (e == hipSuccess) e = hipEventRecord(ev[1], r->stream);
+        if (e == hipSuccess) st = save_particles(r, tmp, true);          // back to the loaded order
+        if (e == hipSuccess && st == PIC_OK) e = hipEventRecord(ev[2], r->stream);
+        if (e == hipSuccess && st == PIC_OK)
+            e = launch_sort(r->dev, r->p.np, r->p.ng, r->p.precision, r->host.sort_scratch, r->stream);
+        if (e == hipSuccess && st == PIC_OK) {
+            r->swapped = !r->swapped;                                    // the sort swapped the arrays
+            e = hipEventRecord(ev[3], r->stream);
+        }
+        if (e == hipSuccess && st == PIC_OK) {
+            e = hipEventSynchronize(ev[3]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t_u, ev[0], ev[1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t_sort, ev[2], ev[3]);
+        }
+        if (e == hipSuccess && st == PIC_OK) e = hipEventRecord(ev[0], r->stream);
+        for (int k = 0; k < kReps && e == hipSuccess && st == PIC_OK; ++k) e = pass();
+        if (e == hipSuccess && st == PIC_OK) e = hipEventRecord(ev[1], r->stream);
+        if (e == hipSuccess && st == PIC_OK) e = hipEventSynchronize(ev[1]);
+        if (e == hipSuccess && st == PIC_OK) e = hipEventElapsedTime(&t_s, ev[0], ev[1]);
+        // the loaded state again, now in the arrays the sort made current
+        if (e == hipSuccess && st == PIC_OK) st = save_particles(r, tmp, true);
+    }
+    const hipError_t se = hipStreamSynchronize(r->stream);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    (void)hipFree(tmp);
+    if (st != PIC_OK) return st;
+    if (e != hipSuccess) return fail(PIC_EDEVICE, "sort-period trial: %s", hipGetErrorString(e));
+    if (se != hipSuccess) return fail(PIC_EDEVICE, "sort-period trial: %s", hipGetErrorString(se));
+    t_u /= kReps;
+    t_s /= kReps;
+    int k = 0;
+    if (t_s < t_u) {
+        const double steps = std::ceil(2.0 * (double)t_sort / (double)(t_u - t_s));
+        k = (int)std::max(1.0, std::min(steps, (double)(1 << 20)));
+    }
+    r->p.sort_every = k;
+    return PIC_OK;
+}
+
 pic_status check_run(pic_run *r) {
     if (!r) return fail(PIC_EINVAL, "run is NULL");
     if (r->error) return fail(PIC_ESTATE, "run is in an error state after an earlier device error");
@@ -525,6 +592,7 @@ pic_status create_run(const pic_params *params, void *dev_mem, size_t dev_bytes,
     pic_status st = fill(r);
     if (st == PIC_OK) st = init_device_state(r);
     if (st == PIC_OK) st = choose_shape(r, d);
+    if (st == PIC_OK && r->p.sort_every == PIC_SORT_AUTO) st = choose_sort_period(r);
     if (st != PIC_OK) {
         std::string msg = g_err;
         (void)hipStreamSynchronize(r->stream);
@@ -598,11 +666,19 @@ pic_status enqueue_step(pic_run *r, const StepEvents *ev = nullptr) {
 
 }  // namespace
 
+extern "C" pic_status pic_sort_period(pic_run *r, int32_t *k) {
+    pic_status st = check_run(r);
+    if (st != PIC_OK) return st;
+    if (!k) return fail(PIC_EINVAL, "k is NULL");
+    *k = r->sort_every();
+    return PIC_OK;
+}
+
 extern "C" pic_status pic_sort(pic_run *r) {
     pic_status st = check_run(r);
     if (st != PIC_OK) return st;
     if (r->batch_member) return fail(PIC_ESTATE, "batch members are sorted by the batch");
-    if (!r->lay.sorting) return fail(PIC_ESTATE, "run was created without cell sorting (sort_every <= 0)");
+    if (!r->lay.sorting) return fail(PIC_ESTATE, "run was created without cell sorting (sort_every = 0)");
     hipError_t e = launch_sort(r->dev, r->p.np, r->p.ng, r->p.precision, r->host.sort_scratch, r->stream);
     if (e != hipSuccess) {
         r->error = true;
@@ -1289,6 +1365,8 @@ pic_status admit_run(pic_batch *b, const pic_params *params, const double *x0, c
     if (!run_id) return fail(PIC_EINVAL, "run_id is NULL");
     if (nsteps < 0) return fail(PIC_EINVAL, "nsteps must be >= 0");
     if (params->precision != PIC_FP32) return fail(PIC_EINVAL, "batched runs use PIC_FP32 state");
+    if (params->sort_every == PIC_SORT_AUTO)
+        return fail(PIC_EINVAL, "batched runs take sort_every >= 0 (PIC_SORT_AUTO is for single runs)");
     if (params->ng > b->cfg.ng_max) return fail(PIC_EINVAL, "ng %d exceeds the batch's ng_max %d", params->ng, b->cfg.ng_max);
     if (b->free_slots.empty()) return fail(PIC_EBUDGET, "run table full (%d runs)", b->cfg.max_runs);
     if (!ld) {

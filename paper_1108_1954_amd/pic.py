@@ -24,12 +24,13 @@ PIC_HIST_COLS = 4
 PIC_FLAG_NONFINITE, PIC_FLAG_MULTIWRAP, PIC_FLAG_SORT = 1, 2, 4
 PIC_SOLVE_EXACT, PIC_SOLVE_CG_PAPER = 0, 1
 PIC_BEAMS_ONE, PIC_BEAMS_ALTERNATE, PIC_BEAMS_RANDOM = 0, 1, 2
+PIC_SORT_AUTO = -1
 
 SYMBOLS = (
     "pic_last_error", "pic_version", "pic_footprint", "pic_create", "pic_create_loaded", "pic_sort",
     "pic_step", "pic_step_graph", "pic_batch_admit_loaded",
     "pic_step_profiled", "pic_batch_step_profiled", "pic_diagnostics", "pic_read_particles", "pic_read_raw", "pic_read_grid", "pic_read_history",
-    "pic_phase_space", "pic_destroy", "pic_batch_create", "pic_batch_admit", "pic_batch_step", "pic_batch_poll",
+    "pic_phase_space", "pic_sort_period", "pic_destroy", "pic_batch_create", "pic_batch_admit", "pic_batch_step", "pic_batch_poll",
     "pic_batch_run", "pic_batch_release", "pic_batch_usage", "pic_batch_destroy",
 )
 
@@ -106,6 +107,7 @@ def load(path: str = LIB_PATH):
         "pic_create_loaded": [P, C.POINTER(pic_loader), vp, sz, vp, C.POINTER(vp)],
         "pic_batch_admit_loaded": [vp, P, C.POINTER(pic_loader), i64, C.POINTER(i64)],
         "pic_sort": [vp],
+        "pic_sort_period": [vp, C.POINTER(i32)],
         "pic_step": [vp, i64],
         "pic_step_graph": [vp, i64, i32],
         "pic_step_profiled": [vp, i64, dptr, dptr],
@@ -239,6 +241,14 @@ def pic_read_raw(run, np_: int, precision: int = PIC_FP32) -> Tuple[np.ndarray, 
     return u, w
 
 
+def pic_sort_period(run) -> int:
+    """The run's cell-sort period K (0: never), as chosen at creation for
+    sort_every = PIC_SORT_AUTO."""
+    k = C.c_int32(0)
+    _check(load().pic_sort_period(run, C.byref(k)))
+    return k.value
+
+
 def pic_phase_space(run, nx: int, nv: int, vmin: float, vmax: float) -> Tuple[np.ndarray, int]:
     """Device-binned (x, v) counts as an (nv, nx) uint32 image, and the
     number of particles with v outside [vmin, vmax)."""
@@ -362,6 +372,9 @@ class Run:
 
     def sort(self) -> None:
         pic_sort(self.handle)
+
+    def sort_period(self) -> int:
+        return pic_sort_period(self.handle)
 
     def diagnostics(self, grids: bool = False):
         return pic_diagnostics(self.handle, self.params.ng if grids else 0)

@@ -74,7 +74,7 @@ def good(**kw):
     dict(ng=1), dict(ng=P.PIC_MAX_NG + 1), dict(np=0), dict(np=1 << 31), dict(L=0.0),
     dict(L=float("nan")), dict(dt=0.0), dict(dt=-1.0), dict(qm=0.0), dict(rho0=0.0),
     dict(precision=2), dict(tile=100), dict(tile=-256), dict(tile=512), dict(history_cap=-1),
-    dict(solver=2), dict(solver=-1), dict(cg_iters=-1), dict(cg_iters=100001),
+    dict(solver=2), dict(solver=-1), dict(cg_iters=-1), dict(cg_iters=100001), dict(sort_every=-2),
 ])
 def test_footprint_rejects_invalid_parameters(lib, bad):
     with pytest.raises(P.PicError) as e:
@@ -149,3 +149,8 @@ def test_loader_rejects_invalid_parameters(lib, bad):
     with pytest.raises(P.PicError) as e:
         P.pic_create_loaded(good(), ld)
     assert e.value.status == P.PIC_EINVAL
+
+
+def test_auto_sort_period_reserves_the_sort_room(lib):
+    auto = P.pic_footprint(good(np=100_000, sort_every=P.PIC_SORT_AUTO))
+    assert auto == P.pic_footprint(good(np=100_000, sort_every=7)) > P.pic_footprint(good(np=100_000))

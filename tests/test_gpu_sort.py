@@ -130,3 +130,44 @@ def test_batched_sorting_runs_equal_the_same_runs_alone():
             np.testing.assert_array_equal(P.pic_read_history(view, 0, s.nsteps), hist)
     finally:
         P.pic_batch_destroy(b)
+
+
+def test_auto_sort_period_leaves_no_trace_and_equals_its_fixed_period():
+    """sort_every = PIC_SORT_AUTO: the creation-time trial (passes on the
+    loaded state, a sort, passes on the sorted state) puts the state back,
+    and the run then behaves exactly like one created with the period it
+    chose."""
+    spec = I.warm_two_stream_large(np_=2_000_003, ng=1024, nsteps=30, L=0.032 * 1024)
+    x, v = spec.particles()
+
+    def params(k):
+        return P.make_params(spec.L, spec.ng, spec.np_, spec.dt, sort_every=k, history_cap=spec.nsteps)
+    with P.Run(params(P.PIC_SORT_AUTO), x, v) as a, P.Run(params(0), x, v) as z:
+        k = a.sort_period()
+        print(f"auto sort period np={spec.np_} ng={spec.ng}: K = {k}", flush=True)
+        assert k >= 0 and z.sort_period() == 0
+        for ra, rz in zip(a.raw(), z.raw()):
+            np.testing.assert_array_equal(ra, rz)
+        for ga, gz in zip(a.grid(), z.grid()):
+            np.testing.assert_array_equal(ga, gz)
+        with P.Run(params(k), x, v) as b:
+            a.step(spec.nsteps, graph_steps=10)
+            b.step(spec.nsteps, graph_steps=10)
+            for ra, rb in zip(a.raw(), b.raw()):
+                np.testing.assert_array_equal(ra, rb)
+            np.testing.assert_array_equal(a.history(), b.history())
+            da, _, _ = a.diagnostics()
+            assert da["step"] == spec.nsteps and da["flags"] == 0
+
+
+def test_batches_reject_the_auto_sort_period():
+    spec = I.two_stream_small(np_=3_000, nsteps=5)
+    x, v = spec.particles()
+    b = P.pic_batch_create(1 << 26, 64, max_runs=2, graph_steps=0, stream=P.current_stream())
+    try:
+        with pytest.raises(P.PicError) as e:
+            P.pic_batch_admit(b, P.make_params(spec.L, spec.ng, spec.np_, spec.dt, sort_every=P.PIC_SORT_AUTO),
+                              x, v, spec.nsteps)
+        assert e.value.status == P.PIC_EINVAL
+    finally:
+        P.pic_batch_destroy(b)
