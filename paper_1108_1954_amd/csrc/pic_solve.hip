@@ -87,55 +87,75 @@ __device__ double solve_exclusive_scan(double v, double *red2, int &par, int nth
 // gradient on the three-point system with the potential at node 0 held at
 // zero (its row is the identity, its residual zero), started from zero and
 // run for a fixed number of iterations, then the central-difference field.
-// Thread tid owns nodes tid, tid + 256, ... (up to kMaxNg / 256 of them)
-// and keeps its potential, residual and A d in registers; the search
-// direction d lives in LDS for the stencil.  The dot products are sums in a
-// fixed order.  On entry D[g] holds S_g; on exit D[g] holds E_g.
+// Each thread owns up to kCgPer strided nodes and keeps their potential,
+// residual and A d in registers; the dot products are sums in a fixed
+// order.  On entry D[g] holds S_g; on exit D[g] holds E_g.
 constexpr int kCgPer = 8;   // nodes per thread: ng <= 8 solve_threads(ng)
 constexpr int kCgWaveMaxNg = 64 * kCgPer;   // grids one wavefront solves alone
 
-// The same CG on one wavefront, for ng <= 512: lane l owns nodes l, l + 64,
-// ...; the dot products are wavefront butterflies and the stencil reads the
-// direction d from LDS written by the same wavefront (LDS operations of a
-// wavefront complete in order), so no workgroup barrier is needed.
+// v of lane i - 1 (lane 0: fill) and of lane i + 1 (lane 63: fill).
+__device__ __forceinline__ double lane_prev(double v, double fill) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_next(double v, double fill) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// One node's row of the CG system applied to d: the identity at node 0,
+// d_{g-1} - 2 d_g + d_{g+1} elsewhere, with d_ng = 0 beyond the last node.
+__device__ __forceinline__ double cg_row(int g, int ng, double left, double mid, double right) {
+    if (g == 0) return mid;
+    return left - 2.0 * mid + (g + 1 < ng ? right : 0.0);
+}
+
+// The direction update d <- beta d + r (every thread that needs a value of
+// d, its own or a neighbour's, forms it with this same expression).
+__device__ __forceinline__ double cg_next_d(double beta, double d, double r) { return __builtin_fma(beta, d, r); }
+
+// The CG on one wavefront, for ng <= 512: lane l owns nodes l, l + 64, ...;
+// the neighbours across the ends of a row of 64 nodes come from lanes 63
+// and 0 of the adjacent rows (readlane), so no LDS or barrier is needed.
 __device__ __forceinline__ void cg_paper_wave(RunDev *R, double *D, double meanS) {
     const int ng = R->ng, lane = threadIdx.x & 63;
     const double dx = R->dx, qf = R->qfac;
-    double ph[kCgPer], r[kCgPer], z[kCgPer];
+    double ph[kCgPer], r[kCgPer], d[kCgPer];
     double rr = 0.0;
 #pragma unroll
     for (int k = 0; k < kCgPer; ++k) {
         const int g = k * 64 + lane;
         ph[k] = 0.0;
-        z[k] = 0.0;
         r[k] = (g > 0 && g < ng) ? -(qf * (D[g] - meanS)) * dx * dx : 0.0;
+        d[k] = r[k];
         rr += r[k] * r[k];
     }
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int k = 0; k < kCgPer; ++k) {
-        const int g = k * 64 + lane;
-        if (g < ng) D[g] = r[k];
-    }
     rr = wave_sum(rr);
-    __builtin_amdgcn_wave_barrier();
+    const int rows = (ng + 63) >> 6;                   // rows of 64 nodes that hold nodes
     if (__builtin_sqrt(rr) > 1e-16) {
         const int iters = R->cg_iters;
         for (int it = 0; it < iters; ++it) {
+            double z[kCgPer];
             double zd = 0.0;
 #pragma unroll
             for (int k = 0; k < kCgPer; ++k) {
-                const int g = k * 64 + lane;
-                if (g < ng) {
-                    double zk;
-                    if (g == 0) {
-                        zk = D[0];
-                    } else {
-                        const double right = g + 1 < ng ? D[g + 1] : 0.0;
-                        zk = D[g - 1] - 2.0 * D[g] + right;
+                z[k] = 0.0;
+                if (k < rows) {                                                          // uniform
+                    const int g = k * 64 + lane;
+                    const double below = k > 0 ? lane_value(d[k - 1], 63) : 0.0;            // node 64 k - 1
+                    const double above = k + 1 < rows ? lane_value(d[k + 1], 0) : 0.0;      // node 64 (k + 1)
+                    const double left = lane_prev(d[k], below), right = lane_next(d[k], above);
+                    if (g < ng) {
+                        z[k] = cg_row(g, ng, left, d[k], right);
+                        zd += z[k] * d[k];
                     }
-                    z[k] = zk;
-                    zd += zk * D[g];
                 }
             }
             zd = wave_sum(zd);
@@ -146,20 +166,18 @@ __device__ __forceinline__ void cg_paper_wave(RunDev *R, double *D, double meanS
             for (int k = 0; k < kCgPer; ++k) {
                 const int g = k * 64 + lane;
                 if (g < ng) {
-                    ph[k] += alpha * D[g];
+                    ph[k] += alpha * d[k];
                     r[k] -= alpha * z[k];
                     rn += r[k] * r[k];
                 }
             }
             rn = wave_sum(rn);
             const double beta = rn / rr;
-            __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int k = 0; k < kCgPer; ++k) {
                 const int g = k * 64 + lane;
-                if (g < ng) D[g] = beta * D[g] + r[k];
+                if (g < ng) d[k] = cg_next_d(beta, d[k], r[k]);
             }
-            __builtin_amdgcn_wave_barrier();
             rr = rn;
         }
     }
@@ -170,23 +188,30 @@ __device__ __forceinline__ void cg_paper_wave(RunDev *R, double *D, double meanS
         if (g < ng) D[g] = ph[k];
     }
     __builtin_amdgcn_wave_barrier();
+    double e[kCgPer];
 #pragma unroll
     for (int k = 0; k < kCgPer; ++k) {
         const int g = k * 64 + lane;
         if (g < ng) {
             const double right = D[g + 1 < ng ? g + 1 : 0];
             const double left = D[g == 0 ? ng - 1 : g - 1];
-            z[k] = -(right - left) / (2.0 * dx);
+            e[k] = -(right - left) / (2.0 * dx);
         }
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int k = 0; k < kCgPer; ++k) {
         const int g = k * 64 + lane;
-        if (g < ng) D[g] = z[k];
+        if (g < ng) D[g] = e[k];
     }
 }
 
+// The workgroup CG (ng > 512): thread tid owns nodes tid, tid + nthr, ...
+// with the potential, residual and A d in registers and the direction d in
+// LDS for the stencil (three barriers per iteration: the direction update
+// and the two dot products).  Keeping d in registers as well, with DPP
+// shifts inside a wavefront and an LDS exchange at its ends, measured
+// slower here (12-22% at ng 2048-8192) than these conflict-free LDS reads.
 __device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, int &par, double meanS, int nthr) {
     if (R->ng <= kCgWaveMaxNg) {
         if (threadIdx.x < 64) cg_paper_wave(R, D, meanS);
