@@ -138,12 +138,6 @@ __device__ __forceinline__ void deposit(T s, T w, unsigned long long *Sl, int ng
     deposit_pair(j, F, Sl);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 
 
 // Issue the loads of one block: UNROLL vectors of VEC particles per lane,

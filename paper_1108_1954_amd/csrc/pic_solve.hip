@@ -28,37 +28,6 @@ __host__ __device__ __forceinline__ int solve_threads(int ng) {
     return t < 256 ? 256 : (t > kMaxSolveThreads ? kMaxSolveThreads : t);
 }
 
-// v of lane `lane ^ 1`, `lane ^ 2`, and of the mirrored lane in its half
-// row (i <-> 7 - i) and row (i <-> 15 - i): DPP moves, no LDS.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double lane_read(double v, int lane) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
-}
-
-// Sum over the 64 lanes in a fixed order, the same value in every lane:
-// pairs, quads, half rows and rows of 16 by DPP moves (a + b and b + a are
-// the same double, so every lane of a row holds the same row sum), then
-// the four row sums in lane order.
-__device__ __forceinline__ double wave_sum(double v) {
-    v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
-    v += dpp_move<0x141>(v);   // row_half_mirror
-    v += dpp_move<0x140>(v);   // row_mirror
-    return ((lane_read(v, 0) + lane_read(v, 16)) + lane_read(v, 32)) + lane_read(v, 48);
-}
-
-__device__ __forceinline__ long long wave_sum(long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
 
 // Block reductions.  Each one writes its wavefront totals to one of two
 // alternating LDS buffers and needs a single barrier: the next reduction
