@@ -283,6 +283,30 @@ def main():
                             "particle_steps_per_s": sp.np_ * sp.nsteps / wall}
         log(f"paper workload: {paper}")
 
+    # ------------------ the precision workload: FP32 and FP64 particle state
+    precision = None
+    if not args.no_single:
+        s5 = I.warm_maxwellian_large()
+        precision = {"workload": f"warm Maxwellian, np=2^28, ng={s5.ng}, L={s5.L:.2f}, dt={s5.dt}; "
+                                 "particles drawn on the device (pic_create_loaded)"}
+        for label, prec, bpp in (("fp32_state", P.PIC_FP32, 16), ("fp64_state", P.PIC_FP64, 32)):
+            p5 = P.make_params(s5.L, s5.ng, s5.np_, s5.dt, precision=prec)
+            r5 = P.Run(p5, loader=P.make_loader(**s5.loader))
+            r5.step(args.graph_steps, graph_steps=args.graph_steps)   # warm, incl. graph capture
+            torch.cuda.synchronize()
+            ev0.record()
+            r5.step(K, graph_steps=args.graph_steps)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms5 = ev0.elapsed_time(ev1) / K
+            mp5, msv5 = P.pic_step_profiled(r5.handle, prof_steps)
+            r5.close()
+            precision[label] = {"ms_per_step": ms5, "particle_steps_per_s": s5.np_ / (ms5 * 1e-3),
+                                "particle_pass_ms": mp5, "solve_ms": msv5,
+                                "particle_pass_GBps": bpp * s5.np_ / (mp5 * 1e6),
+                                "bytes_per_particle_step": bpp}
+        log(f"precision workload: {precision}")
+
     # ------------------------------------------------------------- serving
     serving = None
     if not args.no_serving:
@@ -337,6 +361,7 @@ def main():
         "batched_vs_plain": (batched_rate / plain["value"]) if plain else None,
         "single_run": single,
         "paper_weak_scaling_one_gpu": paper,
+        "precision_state": precision,
         "serving": serving,
         "cpu_baseline": cpu,
     }
