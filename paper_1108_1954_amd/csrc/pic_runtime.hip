@@ -1109,11 +1109,13 @@ pic_status rebuild_schedule(pic_batch *b) {
         total += m.run->p.np;
     }
     const int64_t target = std::max<int64_t>(1, total / std::max(1, 2 * b->grid));
+    // at least a tile for every wavefront of the workgroup that takes a chunk
+    const int min_tiles = std::max(1, b->shape.block / 64);
     for (auto &kv : b->members) {
         const Member &m = kv.second;
         if (m.launch_done <= b->launches) continue;
         const int tile = m.run->lay.tile, nt = m.run->lay.ntiles;
-        const int per = (int)std::max<int64_t>(1, (target + tile - 1) / tile);
+        const int per = (int)std::max<int64_t>(min_tiles, (target + tile - 1) / tile);
         const int count = (nt + per - 1) / per;
         for (int c = 0, t0 = 0; t0 < nt; ++c, t0 += per) {
             const int t1 = std::min(nt, t0 + per);
