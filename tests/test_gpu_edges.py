@@ -116,3 +116,24 @@ def test_history_shorter_than_the_run():
         assert e.value.status == P.PIC_EINVAL
         for ra, rb in zip(a.raw(), b.raw()):
             np.testing.assert_array_equal(ra, rb)
+
+
+@pytest.mark.slow
+def test_largest_particle_count_and_grid():
+    """np = 2^31 - 1 (the largest the ABI takes) on the largest grid
+    (8192 nodes), drawn on the device: the charge total np 2^32 is held
+    exactly in int64 (just below 2^63), no flag is raised, and the deposit
+    of the downloaded state is bit-exact against the oracle."""
+    from oracle import oracle as O
+    np_ = (1 << 31) - 1
+    spec = I.warm_maxwellian_large(np_=np_, ng=P.PIC_MAX_NG, nsteps=2)
+    print(f"largest run: np={np_} ng={spec.ng}", flush=True)
+    p = P.make_params(spec.L, spec.ng, np_, spec.dt)
+    with P.Run(p, loader=P.make_loader(**spec.loader)) as r:
+        r.step(2)
+        d, _, _ = r.diagnostics()
+        assert d["step"] == 2 and d["flags"] == 0
+        assert d["charge_fixed_sum"] == np_ << 32
+        u, _ = r.raw()
+        S, _, _ = r.grid()
+    np.testing.assert_array_equal(S, O.deposit_fixed(spec.ng, u))
