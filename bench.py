@@ -12,7 +12,7 @@ launches sized to each run), and a single large warm two-stream run
 (Np = 2^26, Ng = 4096) is timed for reference.  Then the serving load:
 Poisson arrivals at 50 runs/s of runs drawn as the ensemble with 100..2000
 steps, admitted by HBM footprint under a 200 GB budget (and again under
-64 MiB), reporting p50/p99 completion latency and aggregate particle-steps/s.
+40 MiB), reporting p50/p99 completion latency and aggregate particle-steps/s.
 
 Prints ONE JSON line.  Inputs are seeded and synthetic; particle state is
 resident in HBM before the timed region starts.
@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 1 GiB device copies (the reference for rocprofv3 byte counters)")
     ap.add_argument("--serving-tight-runs", type=int, default=300,
-                    help="requests replayed under a 64 MiB budget (0: skip)")
+                    help="requests replayed under a 40 MiB budget (0: skip)")
     return ap.parse_args()
 
 
@@ -319,11 +319,12 @@ def main():
                                "ensemble with steps U{100..2000}, 200 GB budget")
         log(f"serving: {serving}")
         if args.serving_tight_runs > 0:
-            tight = serve.serve_load(rate=args.serving_rate, budget=64 << 20,
+            tight = serve.serve_load(rate=args.serving_rate, budget=40 << 20,
                                      requests=reqs[:args.serving_tight_runs])
-            tight["workload"] = f"first {args.serving_tight_runs} requests of the same load, 64 MiB budget"
+            tight["workload"] = (f"first {args.serving_tight_runs} requests of the same load, 40 MiB budget "
+                                 "(the largest run is ~31 MiB)")
             serving["tight_budget"] = tight
-            log(f"serving (64 MiB): {tight}")
+            log(f"serving (40 MiB): {tight}")
         del reqs
 
     # --------------------------------------------------------- CPU baseline

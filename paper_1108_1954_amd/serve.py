@@ -200,6 +200,12 @@ class Server:
 
     # ---------------------------------------------------------------- loop
     def run(self, requests: Sequence[Request]) -> List[Result]:
+        for r in requests:
+            # a run larger than the whole arena would wait at the head forever
+            need = P.pic_footprint(P.make_params(r.spec.L, r.spec.ng, r.spec.np_, r.spec.dt, r.spec.qm, r.spec.rho0,
+                                                 history_cap=r.nsteps if self.keep_history else 0)) - 256
+            if need > self.budget:
+                raise ValueError(f"request {r.index} needs {need} bytes, more than the {self.budget}-byte budget")
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.index)))
         total = len(pending)
         while len(self.results) < total:

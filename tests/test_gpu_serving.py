@@ -84,3 +84,11 @@ def test_serving_wall_clock_load_with_pipelined_chunks():
     summary = S.summarize(results, 1 << 30)
     assert 0 < summary["p50_latency_s"] <= summary["p99_latency_s"]
     assert summary["particle_steps"] == sum(q.work for q in reqs)
+
+
+def test_a_request_larger_than_the_budget_is_rejected_up_front():
+    reqs = small_requests(3, seed=31, np_scale=0.05)
+    biggest = max(P.pic_footprint(P.make_params(q.spec.L, q.spec.ng, q.spec.np_, q.spec.dt)) for q in reqs)
+    with S.Server(budget=biggest // 2, clock=S.VirtualClock(tick=1e-3)) as srv:
+        with pytest.raises(ValueError, match="budget"):
+            srv.run(reqs)
