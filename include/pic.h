@@ -14,7 +14,8 @@
  *   4. linear charge deposit with the same two-node weights (Sec. 2.3),
  *      particle charge Q = sign(qm) rho0 L / np (Appendix A);
  *   5. periodic three-point Poisson solve and central-difference field
- *      (Sec. 2.2), solved exactly with zero-mean potential.
+ *      (Sec. 2.2), solved exactly with zero-mean potential, or by the
+ *      paper's fixed-iteration CG (PIC_SOLVE_CG_PAPER).
  *
  * Numerics.  Particle state and push in FP32 (PIC_FP32) or FP64 (PIC_FP64).
  * A particle is u = x/dx in [0, ng) and w = v dt/dx; the engine stores

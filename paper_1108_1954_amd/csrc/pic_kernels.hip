@@ -428,6 +428,8 @@ const void *kernel_for(int block, int unroll) {
     switch (block) {
         case 256: return kernel_unroll<T, 256, PUSH>(unroll);
         case 512: return kernel_unroll<T, 512, PUSH>(unroll);
+        case 640: return kernel_unroll<T, 640, PUSH>(unroll);
+        case 768: return kernel_unroll<T, 768, PUSH>(unroll);
         case 1024: return kernel_unroll<T, 1024, PUSH>(unroll);
         default: return nullptr;
     }

@@ -69,7 +69,7 @@ DeviceInfo device_info() {
     d.shape.unroll = 1;
     if (const char *b = getenv("PIC1D_BLOCK")) {
         int v = atoi(b);
-        if (v == 256 || v == 512 || v == 1024) {
+        if (v == 256 || v == 512 || v == 640 || v == 768 || v == 1024) {
             d.shape.block = v;
             d.forced = true;
         }

@@ -346,7 +346,7 @@ def test_results_do_not_depend_on_the_launch_shape(monkeypatch):
     spec = I.warm_two_stream_large(seed=21, np_=200_003, ng=256, nsteps=12, L=0.032 * 256)
     x, v = spec.particles()
     ref = None
-    for block, unroll in [(1024, 1), (512, 2), (256, 4), (1024, 4)]:
+    for block, unroll in [(1024, 1), (512, 2), (256, 4), (1024, 4), (640, 1), (768, 2)]:
         monkeypatch.setenv("PIC1D_BLOCK", str(block))
         monkeypatch.setenv("PIC1D_UNROLL", str(unroll))
         run, p = make_run(spec, history=spec.nsteps, x=x, v=v)
