@@ -88,7 +88,8 @@ bool tune_lookup(const std::string &key, LaunchShape *out) {
 
 hipError_t tune_shapes(const std::string &key, int precision, hipStream_t stream,
                        const std::function<hipError_t(const LaunchShape &)> &launch, LaunchShape *best) {
-    // 640 and 768 threads fit two workgroups per CU at five waves per SIMD
+    // intermediate sizes: 640 threads fit two workgroups per CU at five
+    // waves per SIMD, 768 one of twelve waves; each wins on some workloads
     static const int kBlocks[] = {256, 512, 640, 768, 1024};
     static const int kUnrolls[] = {1, 2, 4};
     constexpr int kReps = 3;
