@@ -12,7 +12,82 @@ import pytest
 from oracle import oracle as O
 import test_oracle_pins as T
 
-# (name, original text, planted mistake)
+
+# Coherent alternative CG solvers: each converges to the same field as the
+# paper's CG (so the converged pins pass), but its iterates before convergence
+# differ.  They are whole-block replacements of the oracle's CG.
+_CG_INIT = """    for (int32_t g = 0; g < ng; ++g) {
+        phi[g] = 0.0;
+        r[g] = g == 0 ? 0.0 : -rho[g] * dx * dx;
+        d[g] = r[g];
+    }"""
+_CG_OP = """            for (int32_t g = 0; g < ng; ++g) {
+                if (g == 0)
+                    z[g] = d[0];
+                else {
+                    double right = g + 1 < ng ? d[g + 1] : 0.0;
+                    z[g] = d[g - 1] - 2.0 * d[g] + right;
+                }
+            }"""
+_CG_PIN_LAST_INIT = _CG_INIT.replace("r[g] = g == 0 ? 0.0", "r[g] = g == ng - 1 ? 0.0")
+_CG_PIN_LAST_OP = """            for (int32_t g = 0; g < ng; ++g) {
+                if (g == ng - 1)
+                    z[g] = d[ng - 1];
+                else {
+                    double left = g > 0 ? d[g - 1] : 0.0;
+                    z[g] = left - 2.0 * d[g] + d[g + 1];
+                }
+            }"""
+_CG_JACOBI_START = """    for (int32_t g = 0; g < ng; ++g)
+        phi[g] = g == 0 ? 0.0 : 0.5 * rho[g] * dx * dx;
+    for (int32_t g = 0; g < ng; ++g) {
+        double right = g + 1 < ng ? phi[g + 1] : 0.0;
+        double aphi = g == 0 ? phi[0] : phi[g - 1] - 2.0 * phi[g] + right;
+        r[g] = (g == 0 ? 0.0 : -rho[g] * dx * dx) - aphi;
+        d[g] = r[g];
+    }"""
+_CG_LOOP = """    if (sqrt(rr) > 1e-16) {
+        for (; it < maxit; ++it) {"""
+_CG_CONJUGATE_RESIDUAL = """    if (sqrt(rr) > 1e-16) {
+        double *ar = (double *)malloc(sz);
+#define APPLY_A(out, in) for (int32_t g = 0; g < ng; ++g) { \\
+            if (g == 0) out[g] = in[0]; \\
+            else { double rt = g + 1 < ng ? in[g + 1] : 0.0; out[g] = in[g - 1] - 2.0 * in[g] + rt; } }
+        APPLY_A(ar, r);
+        for (int32_t g = 0; g < ng; ++g)
+            z[g] = ar[g];
+        double rar = 0.0;
+        for (int32_t g = 0; g < ng; ++g)
+            rar += r[g] * ar[g];
+        for (; it < maxit; ++it) {
+            double zz = 0.0;
+            for (int32_t g = 0; g < ng; ++g)
+                zz += z[g] * z[g];
+            if (zz == 0.0)
+                break;
+            double alpha = rar / zz;
+            for (int32_t g = 0; g < ng; ++g) {
+                phi[g] += alpha * d[g];
+                r[g] -= alpha * z[g];
+            }
+            APPLY_A(ar, r);
+            double rar_new = 0.0;
+            for (int32_t g = 0; g < ng; ++g)
+                rar_new += r[g] * ar[g];
+            double beta = rar_new / rar;
+            for (int32_t g = 0; g < ng; ++g) {
+                d[g] = r[g] + beta * d[g];
+                z[g] = ar[g] + beta * z[g];
+            }
+            rar = rar_new;
+        }
+        free(ar);
+    }
+    if (0) {
+        for (; it < maxit; ++it) {"""
+
+# (name, original text, planted mistake); a mutant may also replace several
+# texts at once (tuples of originals and of mistakes).
 MUTANTS = [
     ("deposit weights swapped", "rho[j0] += (1.0 - f) * qdx;", "rho[j0] += f * qdx;"),
     ("node offset sign", "double t = x / cell_width(p) - 0.5;", "double t = x / cell_width(p) + 0.5;"),
@@ -44,6 +119,9 @@ MUTANTS = [
     ("phase column scale", "double xs = (double)nx / (double)p->ng;", "double xs = (double)nv / (double)p->ng;"),
     ("phase lower velocity edge excluded", "if (!(y >= 0.0 && y < (double)nv)) {",
      "if (!(y > 0.0 && y < (double)nv)) {"),
+    ("cg pins the last node instead of node 0", (_CG_INIT, _CG_OP), (_CG_PIN_LAST_INIT, _CG_PIN_LAST_OP)),
+    ("cg starts from the Jacobi guess", _CG_INIT, _CG_JACOBI_START),
+    ("cg replaced by conjugate residual", _CG_LOOP, _CG_CONJUGATE_RESIDUAL),
 ]
 
 # The pins run against every build (argument lists for the parametrised ones).
@@ -59,6 +137,7 @@ PINS = [
     (T.test_solve_matches_dense_linear_algebra, [(8,), (17,)]),
     (T.test_solve_single_mode_closed_form, [(16, 1), (64, 3)]),
     (T.test_paper_cg_converges_to_exact_solve, [(32,)]),
+    (T.test_paper_cg_iterate_is_the_krylov_projection, [(64, 10), (256, 150)]),
     (T.test_gather_on_nodes_and_linear_field, [()]),
     (T.test_push_uniform_field_closed_form, [()]),
     (T.test_push_wraps_periodically, [()]),
@@ -96,9 +175,12 @@ def test_unmodified_oracle_passes_every_pin(restore_oracle):
 @pytest.mark.parametrize("name,orig,bad", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_planted_mistake_is_caught(name, orig, bad, tmp_path, restore_oracle):
     src = open(O.SRC).read()
-    assert src.count(orig) == 1, f"mutation anchor not unique: {orig}"
+    origs, bads = (orig, bad) if isinstance(orig, tuple) else ((orig,), (bad,))
+    for o, b in zip(origs, bads):
+        assert src.count(o) == 1, f"mutation anchor not unique: {o}"
+        src = src.replace(o, b)
     mutant = tmp_path / "mutant.c"
-    mutant.write_text(src.replace(orig, bad))
+    mutant.write_text(src)
     so = O.build(str(mutant), str(tmp_path / f"libmutant_{abs(hash(name))}.so"))
     O.use_library(so)
     assert failing_pins(), f"no pin caught the planted mistake: {name}"

@@ -196,6 +196,62 @@ def test_paper_cg_converges_to_exact_solve(ng):
     np.testing.assert_allclose(E_cg, E, rtol=0, atol=1e-9 * np.abs(E).max())
 
 
+def krylov_cg_iterate(rho, dx, k):
+    """The k-th iterate of the paper's CG (Sec. 2.2, Sec. 3.3: potential at
+    node 0 held at zero, started from zero), from the property that defines
+    conjugate gradients rather than from their recurrences.
+
+    With phi_0 = 0 the unknowns are phi_1 .. phi_{ng-1}; the closing row uses
+    the periodic image phi_ng = phi_0 = 0, so the system is T phi = b with
+    T = tridiag(1, -2, 1) (negative definite) and b_g = -rho_g dx^2.  Started
+    from zero, the k-th CG iterate minimises the error in the (-T)-norm over
+    the Krylov space span{b, T b, ..., T^(k-1) b}.  Here that space gets an
+    orthonormal basis V (Lanczos with full reorthogonalisation, numpy), and the
+    minimiser is V y with (V^T (-T) V) y = V^T (-T) phi* = -V^T b (the Galerkin
+    condition; T phi* = b).  E follows by the periodic central difference."""
+    ng = rho.size
+    n = ng - 1
+    b = -np.asarray(rho[1:], dtype=np.float64) * dx * dx
+    T = -2.0 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1)
+    V = np.zeros((n, k))
+    V[:, 0] = b / np.linalg.norm(b)
+    for j in range(1, k):
+        w = T @ V[:, j - 1]
+        for _ in range(2):                              # full reorthogonalisation, twice
+            w -= V[:, :j] @ (V[:, :j].T @ w)
+        V[:, j] = w / np.linalg.norm(w)
+    y = np.linalg.solve(V.T @ (-T) @ V, -(V.T @ b))
+    phi = np.concatenate([[0.0], V @ y])
+    return -(np.roll(phi, -1) - np.roll(phi, 1)) / (2 * dx)
+
+
+@pytest.mark.parametrize("ng,k", [(64, 10), (64, 30), (256, 150), (2048, 150)])
+def test_paper_cg_iterate_is_the_krylov_projection(ng, k):
+    """Before it converges, the paper's fixed-iteration CG is pinned iterate by
+    iterate: after k iterations its field equals the field of the Krylov
+    projection above (computed with dense linear algebra, independent of the
+    CG recurrences) to 1e-9 of max|E| (measured: 1e-12 and below).  The grids
+    include ng = 256 and 2048 at the paper's 150 iterations, where the CG is
+    still far from the exact solve (relative difference 0.2 and 0.7).  A
+    different pinned node, start vector or Krylov method (conjugate residual)
+    converges to the same field but fails here."""
+    L = 0.032 * ng
+    dx = L / ng
+    if ng <= 256:
+        rho = np.random.default_rng(ng + k).normal(size=ng)
+    else:                                               # a particle deposit at the large grid
+        x, _ = I.two_stream_small(np_=20_000).particles()
+        rho = O.density(O.params(2.053, ng, x.size), x * (L / 2.053), O.DEPOSIT_PLAIN)
+    rho = rho - rho.mean()
+    p = O.params(L, ng, 1)
+    _, E_cg, it = O.cg_paper(p, rho, maxit=k)
+    assert it == k
+    E_ref = krylov_cg_iterate(rho, dx, k)
+    np.testing.assert_allclose(E_cg, E_ref, rtol=0, atol=1e-9 * np.abs(E_ref).max())
+    E_exact, _ = O.solve(p, rho)
+    assert np.abs(E_cg - E_exact).max() > 1e-3 * np.abs(E_exact).max()     # not converged yet
+
+
 def test_paper_cg_150_iterations_unconverged_at_large_grid():
     """At ng = 2048 the fixed 150 CG iterations leave a large error: the reason
     the exact solve is used instead (reading R2)."""
