@@ -223,6 +223,16 @@ pic_status pic_step_graph(pic_run *run, int64_t nsteps, int32_t graph_steps);
  * measurement; the steps are real and advance the run. */
 pic_status pic_step_profiled(pic_run *run, int64_t nsteps, double *ms_particle, double *ms_solve);
 
+/* Achievable-bandwidth reference of the particle pass (measurement only, no
+ * part of the method): swaps the contents of the device arrays a[n] and
+ * b[n] of FP32 values, `reps` >= 1 times on `stream`, with the pass's memory
+ * pattern (16-byte non-temporal loads and stores, all CUs) and nothing
+ * else, i.e. 16 bytes per element pair per swap, and reports the mean
+ * duration of one swap in milliseconds (HIP events; waits for them).
+ * a and b are caller-owned device buffers, 16-byte aligned, n a multiple
+ * of 4 (else EINVAL); their contents end swapped if reps is odd. */
+pic_status pic_bandwidth_probe(void *a, void *b, int64_t n, int32_t reps, void *stream, double *ms);
+
 /* Synchronise the run's stream and report diagnostics of the current state.
  * rho_out/E_out (FP64, ng_cap >= ng entries) may be NULL. */
 pic_status pic_diagnostics(pic_run *run, pic_diag *diag, double *rho_out, double *E_out,
@@ -316,6 +326,14 @@ pic_status pic_batch_poll(pic_batch *b, int64_t *done_ids, int32_t cap, int32_t 
 /* Borrow the pic_run view of a batch member, valid until its release; the
  * read/diagnostic calls above work on it (pic_step/pic_destroy do not). */
 pic_status pic_batch_run(pic_batch *b, int64_t run_id, pic_run **view);
+
+/* Diagnostics of batch member `run_id` (as pic_diagnostics, without the
+ * grids): its step count N and the energies, momentum and charge of its state
+ * after N steps (Sec. 2 model; the sums are defined at pic_diag).  Waits for
+ * the work queued on the batch stream unless the member was already
+ * reported complete by pic_batch_poll, in which case it reads without
+ * waiting for the other members.  EINVAL for an unknown or released id. */
+pic_status pic_batch_diagnostics(pic_batch *b, int64_t run_id, pic_diag *diag);
 
 /* Retire a run: its table slot and arena space become free for later
  * admissions at once.  Asynchronous and safe while work is queued: reuse is

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("pic_kernels.hip", "pic_solve.hip", "pic_sort.hip", "pic_loader.hip", "pic_phase.hip", "pic_tune.hip", "pic_runtime.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("pic_kernels.hip", "pic_solve.hip", "pic_sort.hip", "pic_loader.hip", "pic_phase.hip", "pic_probe.hip", "pic_tune.hip", "pic_runtime.hip")]
 LIB = os.path.join(HERE, "libpic1d.so")
 ARCH = os.environ.get("PIC1D_ARCH", "gfx950")
 

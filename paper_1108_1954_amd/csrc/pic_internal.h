@@ -158,6 +158,10 @@ hipError_t launch_phase(const void *u, const void *w, int64_t np, int precision,
 hipError_t launch_loader(void *u, void *w, int64_t np, int ng, int precision, const LoaderArgs &a, int cus,
                          hipStream_t stream);
 
+// Bandwidth reference (pic_probe.hip): swap two device arrays of nvec
+// 16-byte vectors (the particle pass's bytes, nothing else).
+hipError_t launch_swap(void *a, void *b, int64_t nvec, int cus, hipStream_t stream);
+
 // Autotuner (pic_tune.hip).  tune_key names a size class; tune_lookup finds
 // a cached shape; tune_shapes times `launch(shape)` (one particle pass on
 // saved state) for every candidate and caches and returns the fastest.

@@ -799,6 +799,30 @@ extern "C" pic_status pic_step_profiled(pic_run *r, int64_t nsteps, double *ms_p
     return st;
 }
 
+extern "C" pic_status pic_bandwidth_probe(void *a, void *b, int64_t n, int32_t reps, void *stream,
+                                          double *ms) {
+    if (!a || !b || !ms) return fail(PIC_EINVAL, "a, b and ms must not be NULL");
+    if (n < 4 || n % 4 != 0 || reps < 1 || (uintptr_t)a % 16 || (uintptr_t)b % 16)
+        return fail(PIC_EINVAL, "need n a positive multiple of 4, reps >= 1, 16-byte aligned arrays");
+    hipStream_t s = (hipStream_t)stream;
+    const int cus = device_info().cus;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch_swap(a, b, n / 4, cus, s);                    // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) e = launch_swap(a, b, n / 4, cus, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(PIC_EDEVICE, "bandwidth probe: %s", hipGetErrorString(e));
+    *ms = (double)t / reps;
+    return PIC_OK;
+}
+
 extern "C" pic_status pic_diagnostics(pic_run *r, pic_diag *diag, double *rho_out, double *E_out,
                                       int32_t ng_cap) {
     pic_status st = check_run(r);
@@ -1674,6 +1698,16 @@ extern "C" pic_status pic_batch_run(pic_batch *b, int64_t run_id, pic_run **view
     if (it == b->members.end()) return fail(PIC_EINVAL, "unknown run id %lld", (long long)run_id);
     *view = it->second.run;
     return PIC_OK;
+}
+
+extern "C" pic_status pic_batch_diagnostics(pic_batch *b, int64_t run_id, pic_diag *diag) {
+    pic_run *view = nullptr;
+    pic_status st = pic_batch_run(b, run_id, &view);
+    if (st != PIC_OK) return st;
+    if (!diag) return fail(PIC_EINVAL, "diag is NULL");
+    st = pic_diagnostics(view, diag, nullptr, nullptr, 0);
+    if (st == PIC_EDEVICE) b->error = true;
+    return st;
 }
 
 extern "C" pic_status pic_batch_release(pic_batch *b, int64_t run_id) {

@@ -31,7 +31,7 @@ SYMBOLS = (
     "pic_step", "pic_step_graph", "pic_batch_admit_loaded",
     "pic_step_profiled", "pic_batch_step_profiled", "pic_diagnostics", "pic_read_particles", "pic_read_raw", "pic_read_grid", "pic_read_history",
     "pic_phase_space", "pic_sort_period", "pic_destroy", "pic_batch_create", "pic_batch_admit", "pic_batch_step", "pic_batch_poll",
-    "pic_batch_run", "pic_batch_release", "pic_batch_usage", "pic_batch_destroy",
+    "pic_bandwidth_probe", "pic_batch_run", "pic_batch_diagnostics", "pic_batch_release", "pic_batch_usage", "pic_batch_destroy",
 )
 
 
@@ -119,11 +119,13 @@ def load(path: str = LIB_PATH):
         "pic_read_history": [vp, i64, i64, vp],
         "pic_phase_space": [vp, i32, i32, C.c_double, C.c_double, vp, C.POINTER(i64)],
         "pic_destroy": [vp],
+        "pic_bandwidth_probe": [vp, vp, i64, i32, vp, dptr],
         "pic_batch_create": [C.POINTER(pic_batch_config), vp, C.POINTER(vp)],
         "pic_batch_admit": [vp, P, dptr, dptr, i64, C.POINTER(i64)],
         "pic_batch_step": [vp, i64],
         "pic_batch_poll": [vp, vp, i32, C.POINTER(i32)],
         "pic_batch_run": [vp, i64, C.POINTER(vp)],
+        "pic_batch_diagnostics": [vp, i64, C.POINTER(pic_diag)],
         "pic_batch_release": [vp, i64],
         "pic_batch_usage": [vp, C.POINTER(sz), C.POINTER(sz), C.POINTER(i32)],
         "pic_batch_destroy": [vp],
@@ -314,6 +316,20 @@ def pic_batch_run(batch, run_id: int) -> C.c_void_p:
     out = C.c_void_p()
     _check(load().pic_batch_run(batch, int(run_id), C.byref(out)))
     return out
+
+
+def pic_bandwidth_probe(a: int, b: int, n: int, reps: int = 10, stream: Optional[int] = None) -> float:
+    """Mean ms of one swap of two device FP32 arrays of n values (device
+    pointers a, b): the particle pass's bytes without its work."""
+    ms = C.c_double(0)
+    _check(load().pic_bandwidth_probe(a, b, int(n), int(reps), stream, C.byref(ms)))
+    return ms.value
+
+
+def pic_batch_diagnostics(batch, run_id: int) -> dict:
+    d = pic_diag()
+    _check(load().pic_batch_diagnostics(batch, int(run_id), C.byref(d)))
+    return d.as_dict()
 
 
 def pic_batch_release(batch, run_id: int) -> None:
