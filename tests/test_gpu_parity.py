@@ -14,6 +14,8 @@ from oracle import oracle as O
 from paper_1108_1954_amd import inputs as I
 from paper_1108_1954_amd import pic as P
 
+import history_check as HC
+
 pytestmark = pytest.mark.gpu
 
 EPS32 = 2.0 ** -24
@@ -186,33 +188,51 @@ def test_graph_replay_is_bit_identical_to_plain_launches():
 
 # ----------------------------------------------------- runs vs the oracle ---
 
-@pytest.mark.parametrize("precision,lin_tol", [(P.PIC_FP32, 1e-3), (P.PIC_FP64, 1e-9)])
-def test_two_stream_history_against_fp64_oracle(precision, lin_tol):
-    """Two-stream run (Ng=64, Np=10,000, 200 steps): W_E history of the
-    engine (FP32 or FP64 state, fixed-point deposit) vs the plain FP64
-    oracle from the same FP64 inputs.  FP32 state: positions round once to
-    2^-24 relative, which the linear instability carries along; FP64 state:
-    only FP64 rounding in another operation order, amplified by e^{gamma t}
-    (~30x by t = 10), plus the 2^-32 quantisation of the deposit weights."""
+@pytest.mark.parametrize("precision", [P.PIC_FP32, P.PIC_FP64])
+def test_two_stream_history_against_fp64_oracle(precision):
+    """Two-stream run (Ng=64, Np=10,000, 200 steps): every column of the
+    engine's history (KE^n, W_E^n, P^{n+1/2}, K^{n+1/2}) and the diagnostics
+    after creation and after the last step against the FP64 oracle's steps
+    from the same FP64 inputs with the same fixed-point deposit rule.  The
+    bounds come from the oracle's own sensitivity to one rounding of the state
+    to the engine's precision (tests/history_check.py): over the linear phase
+    (100 steps, t < 10) and over the whole run."""
     spec = I.two_stream_small()
     x, v = spec.particles()
     run, p = make_run(spec, precision=precision, history=spec.nsteps, x=x, v=v)
     with run:
+        d0, _, _ = run.diagnostics()
         run.step(spec.nsteps)
         h = run.history()
-    ref = O.run(oracle_params(p), x, v, spec.nsteps, mode=O.DEPOSIT_PLAIN)["hist"]
-    we, we_o = h[:, 1], ref[:, 1]
-    lin = slice(0, 100)                                   # linear phase, t < 10
-    err_lin = np.abs(we[lin] - we_o[lin]).max() / we_o[lin].max()
-    err_all = np.abs(we - we_o).max() / we_o.max()
-    print(f"two-stream W_E vs FP64 oracle, precision {precision}: linear phase {err_lin:.3e}, "
-          f"200 steps {err_all:.3e}", flush=True)
-    assert err_lin < lin_tol, err_lin
-    # momentum conserved to rounding; energy as well as the oracle's
-    m = O.particle_mass(oracle_params(p))
-    assert np.abs(h[:, 2] - h[0, 2]).max() < 1e-5 * m * np.abs(v).sum()
-    et = h[:, 0] + h[:, 1]
-    assert np.abs(et[:100] - et[0]).max() / et[0] < 3e-4
+        d1, _, _ = run.diagnostics()
+    op = oracle_params(p)
+    lin, n = 100, spec.nsteps
+    dtype = np.float32 if precision == P.PIC_FP32 else np.float64
+    bounds, ref, sens = HC.state_bounds(op, x, v, n, (lin, n), dtype=dtype)
+    pscale = HC.momentum_scale(op, v)
+    err = HC.column_errors(h, ref, pscale)
+    for window in (lin, n):
+        for c in HC.COLS:
+            e, bnd = float(err[c][:window].max()), bounds[window][c]
+            print(f"two-stream {dtype.__name__} state, {c} over {window} steps: error {e:.3e}, "
+                  f"bound {bnd:.3e} (one rounding moves it {float(sens[c][:window].max()):.3e})", flush=True)
+            assert e <= bnd, (c, window, e, bnd)
+    # diagnostics of the state after creation: (m/2) sum v^2 and m sum v of
+    # the inputs, from the oracle's push with zero field (its sums of v_old);
+    # each stored w rounds once to the state precision, the FP64 sums of np
+    # terms in another order
+    eps = EPS32 if precision == P.PIC_FP32 else EPS64
+    m = O.particle_mass(op)
+    _, _, acc = O.push(op, x, v, np.zeros(p.np))
+    k0 = 0.5 * m * acc[0]
+    assert abs(d0["kinetic"] - k0) <= (4 * eps + (p.np + 8) * EPS64) * k0
+    assert abs(d0["momentum"] - m * float(np.sum(v))) <= (2 * eps + (p.np + 8) * EPS64) * pscale
+    assert d0["step"] == 0 and d1["step"] == n
+    # after the last step: K^{N-1/2} and P^{N-1/2}, the oracle's last row
+    kscale = np.abs(ref[:, 3]).max()
+    assert d1["kinetic"] == h[-1, 3] and d1["momentum"] == h[-1, 2]
+    assert abs(d1["kinetic"] - ref[-1, 3]) <= bounds[n]["K"] * kscale
+    assert abs(d1["momentum"] - ref[-1, 2]) <= bounds[n]["P"] * pscale
 
 
 def test_cold_plasma_frequency_on_gpu():
@@ -358,3 +378,45 @@ def test_results_do_not_depend_on_the_launch_shape(monkeypatch):
         else:
             for a, b in zip(ref, got):
                 np.testing.assert_array_equal(a, b)
+
+
+def test_batch_diagnostics_of_a_live_member_against_the_oracle():
+    """pic_batch_diagnostics on a batch member that is still running (the
+    two-stream run, 60 of its 200 steps taken, beside another run): the step
+    count and exact charge, the kinetic energy K^{N-1/2}, the momentum
+    P^{N-1/2} and the field energy W_E^N against the FP64 oracle's run of
+    the same inputs, within the history bounds of the FP32 state; the same
+    values as pic_diagnostics on the member's view; EINVAL for an unknown id."""
+    spec = I.two_stream_small()
+    other = small_ensemble(1, seed=5)[0]
+    x, v = spec.particles()
+    n = 60
+    b = P.pic_batch_create(1 << 28, 2048, max_runs=4, graph_steps=8, stream=P.current_stream())
+    try:
+        p = P.make_params(spec.L, spec.ng, spec.np_, spec.dt)
+        rid = P.pic_batch_admit(b, p, x, v, spec.nsteps)
+        P.pic_batch_admit(b, P.make_params(other.L, other.ng, other.np_, other.dt), *other.particles(),
+                          other.nsteps)
+        P.pic_batch_step(b, n)
+        d = P.pic_batch_diagnostics(b, rid)
+        dv, _, _ = P.pic_diagnostics(P.pic_batch_run(b, rid))
+        assert d == dv
+        with pytest.raises(P.PicError) as e:
+            P.pic_batch_diagnostics(b, 10_000)
+        assert e.value.status == P.PIC_EINVAL
+    finally:
+        P.pic_batch_destroy(b)
+    op = oracle_params(p)
+    bounds, _, _ = HC.state_bounds(op, x, v, n + 1, (n + 1,))      # rows 0..n: the field E^n too
+    bounds = bounds[n + 1]
+    out = O.run(op, x, v, n, mode=O.DEPOSIT_FIXED)
+    ref = out["hist"]
+    assert d["step"] == n and d["charge_fixed_sum"] == spec.np_ << 32 and d["flags"] == 0
+    kscale, pscale = np.abs(ref[:, 3]).max(), HC.momentum_scale(op, v)
+    assert abs(d["kinetic"] - ref[-1, 3]) <= bounds["K"] * kscale
+    assert abs(d["momentum"] - ref[-1, 2]) <= bounds["P"] * pscale
+    we = O.field_energy(op, out["E"])
+    assert abs(d["field"] - we) <= bounds["W_E"] * ref[:, 1].max()
+    print(f"batch member diagnostics after {n} steps: kinetic {abs(d['kinetic'] - ref[-1, 3]) / kscale:.2e}, "
+          f"momentum {abs(d['momentum'] - ref[-1, 2]) / pscale:.2e}, field "
+          f"{abs(d['field'] - we) / ref[:, 1].max():.2e} of scale", flush=True)
