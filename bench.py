@@ -59,6 +59,11 @@ def parse():
                     help="only run plain 1 GiB device copies (the reference for rocprofv3 byte counters)")
     ap.add_argument("--serving-tight-runs", type=int, default=300,
                     help="requests replayed under a 40 MiB budget (0: skip)")
+    ap.add_argument("--workload", default="full", choices=("full", "paper", "small", "probe"),
+                    help="full: the benchmark line (default).  For profiling one kernel at a time: "
+                         "paper (the paper's workload, exact solve), small (the first --small-runs runs of "
+                         "the serving load in one batch), probe (the bandwidth reference)")
+    ap.add_argument("--small-runs", type=int, default=8)
     return ap.parse_args()
 
 
@@ -91,22 +96,56 @@ def generate(specs):
         return list(ex.map(lambda s: s.particles(), specs))
 
 
-def cpu_baseline(spec, parts, budget_s=15.0):
-    """The FP64 oracle as it stands, on one host core, on a bounded sample of
-    the workload: one ensemble run, stepped long enough for ~budget_s."""
+def host_threads() -> int:
+    """Host cores this process may use, at most 16 (one GPU's share of the
+    box's cores)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(specs, parts, budget_s=15.0):
+    """The FP64 oracle as it stands (plain FP64 deposit), timed on a bounded
+    sample of the ensemble workload: every run of the ensemble stepped the
+    same number of steps, the runs spread over all host threads (independent
+    runs, one per thread at a time, largest first; the oracle's C code runs
+    outside the GIL), and, for the single-core figure, one thread stepping
+    every run.  Each run's time includes its initial deposit and solve, which
+    are not counted as particle-steps."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
-    x, v = parts
-    p = O.params(spec.L, spec.ng, spec.np_, dt=spec.dt)
+    total = sum(s.np_ for s in specs)
+    order = sorted(range(len(specs)), key=lambda k: -specs[k].np_)
+
+    def one(k, n):
+        s = specs[k]
+        x, v = parts[k]
+        O.run(O.params(s.L, s.ng, s.np_, dt=s.dt), x, v, n, mode=O.DEPOSIT_PLAIN)
+
+    # single core: every run, a few steps (about budget_s / 2)
     t = time.perf_counter()
-    O.run(p, x, v, 2, mode=O.DEPOSIT_FIXED)
-    per_step = (time.perf_counter() - t) / 2
-    n = max(2, int(budget_s / max(per_step, 1e-6)))
+    for k in order:
+        one(k, 1)
+    per_step = time.perf_counter() - t
+    n1 = max(1, int(0.5 * budget_s / max(per_step, 1e-6)))
     t = time.perf_counter()
-    O.run(p, x, v, n, mode=O.DEPOSIT_FIXED)
-    dt = time.perf_counter() - t
-    return {"value": spec.np_ * n / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle (fixed-point deposit), one ensemble run np={spec.np_} ng={spec.ng}, "
-                      f"{n} steps, {dt:.1f} s, single thread",
+    for k in order:
+        one(k, n1)
+    t1 = time.perf_counter() - t
+    # all host threads: every run, steps chosen for about budget_s of wall time
+    threads = host_threads()
+    nall = max(2, int(budget_s * threads / max(per_step, 1e-6)))
+    t = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda k: one(k, nall), order))
+    tall = time.perf_counter() - t
+    return {"value": total * nall / tall, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, plain FP64 deposit, all {len(specs)} ensemble runs ({total} particles) "
+                      f"x {nall} steps each, {threads} threads (independent runs in parallel), {tall:.1f} s",
+            "single_core": {"value": total * n1 / t1, "cores": 1,
+                            "sample": f"the same runs x {n1} steps each on one thread, {t1:.1f} s"},
             "cpu": cpu_model(), "host_cores": os.cpu_count()}
 
 
@@ -135,6 +174,80 @@ def calibrate_copy(reps=4):
     print(json.dumps({"copy_bytes_per_dispatch": COPY_BYTES, "dispatches": reps}), flush=True)
 
 
+def workload_paper(args, P, I, torch):
+    """The paper's weak-scaling workload at its 128-thread size, exact solve,
+    K graph-replayed steps and K profiled ones."""
+    sp = I.paper_weak_scaling(cores=128)
+    pp = P.make_params(sp.L, sp.ng, sp.np_, sp.dt)
+    with P.Run(pp, loader=P.make_loader(**sp.loader)) as rp:
+        rp.step(args.warmup + args.graph_steps, graph_steps=args.graph_steps)    # incl. graph capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rp.step(args.steps, graph_steps=args.graph_steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        mp, ms = P.pic_step_profiled(rp.handle, args.steps)
+    return {"workload": f"paper weak-scaling run, ng={sp.ng}, np={sp.np_}", "ms_per_step": 1e3 * wall / args.steps,
+            "particle_pass_ms": mp, "solve_ms": ms,
+            "particle_pass_GBps": BYTES_PER_PSTEP * sp.np_ / (mp * 1e6)}
+
+
+def workload_small(args, P, I, torch):
+    """The serving regime: the first --small-runs runs of the serving load
+    (drawn as the ensemble, seed 4) in one batch sized like the server's
+    (256 slots, ng up to 2048), stepped from a captured graph."""
+    from paper_1108_1954_amd import serve
+    n = args.small_runs
+    specs = I.ensemble(nruns=n, seed=4, steps_range=(100, 2000))
+    parts = generate(specs)
+    total = sum(s.np_ for s in specs)
+    steps = args.warmup + 2 * args.steps + 2
+    b = P.pic_batch_create(2 << 30, 2048, max_runs=256, graph_steps=10, stream=P.current_stream())
+    try:
+        for s, (x, v) in zip(specs, parts):
+            P.pic_batch_admit(b, P.make_params(s.L, s.ng, s.np_, s.dt), x, v, steps)
+        P.pic_batch_step(b, args.warmup)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        P.pic_batch_step(b, args.steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        mp, msv = P.pic_batch_step_profiled(b, args.steps)
+    finally:
+        P.pic_batch_destroy(b)
+    return {"workload": f"first {n} runs of the serving load in one batch, {total} particles, "
+                        f"ng {sorted(set(s.ng for s in specs))}", "ms_per_step": ms,
+            "particle_pass_ms": mp, "solve_ms": msv, "particle_pass_GBps": BYTES_PER_PSTEP * total / (mp * 1e6)}
+
+
+def workload_probe(args, P, torch, nbytes=2 << 30):
+    """The bandwidth reference: two FP32 arrays of 1 GiB each swapped in
+    place (16 bytes per element pair, the particle pass's pattern), and a
+    plain torch device copy of 1 GiB for comparison."""
+    n = nbytes // 8
+    a = torch.zeros(n, dtype=torch.float32, device="cuda")
+    b = torch.ones(n, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    ms = P.pic_bandwidth_probe(a.data_ptr(), b.data_ptr(), n, reps=args.steps, stream=P.current_stream())
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    mc = ev0.elapsed_time(ev1) / args.steps
+    return {"workload": "bandwidth reference", "swap_bytes": 16 * n, "swap_ms": ms,
+            "swap_GBps": 16 * n / (ms * 1e6), "swap_frac_of_peak": 16 * n / (ms * 1e6) / PEAK_HBM_GBPS,
+            "torch_copy_bytes": 2 * COPY_BYTES, "torch_copy_ms": mc,
+            "torch_copy_GBps": 2 * COPY_BYTES / (mc * 1e6)}
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -152,6 +265,11 @@ def main():
     dev = torch.cuda.get_device_properties(0)
     stream = P.current_stream()
     K, W = args.steps, args.warmup
+    if args.workload != "full":
+        fn = {"paper": lambda: workload_paper(args, P, I, torch), "small": lambda: workload_small(args, P, I, torch),
+              "probe": lambda: workload_probe(args, P, torch)}[args.workload]
+        print(json.dumps(fn()), flush=True)
+        return
 
     # ------------------------------------------------------------ ensemble
     t0 = time.perf_counter()
@@ -330,8 +448,7 @@ def main():
     # --------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
-        k = int(np.argsort([s.np_ for s in specs])[len(specs) // 2])     # median-size run
-        cpu = cpu_baseline(specs[k], parts[k])
+        cpu = cpu_baseline(specs, parts)
         log(f"cpu baseline: {cpu}")
 
     achieved = BYTES_PER_PSTEP * total_np / (ms_particle * 1e6)   # GB/s of the particle pass
