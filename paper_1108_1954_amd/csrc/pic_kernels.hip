@@ -140,6 +140,51 @@ __device__ __forceinline__ void deposit(T s, T w, unsigned long long *Sl, int ng
 
 
 
+// The run's gather table into LDS: Et[g + 1] = tab[g], with the ghosts
+// Et[0] = tab[ng - 1] and Et[ng + 1] = tab[0].  The table (at most 64 KB,
+// 256-byte aligned) is read as 16-byte vectors in rounds of kTableRound
+// vectors per thread, every load of a round issued before any LDS write, so
+// a round costs one memory round trip (one per table in FP32 at 640 threads
+// and ng 8192, instead of one per element per thread).
+constexpr int kTableRound = 4;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int BLOCK>
+__device__ __forceinline__ void fill_table(const T *tab, T *Et, int ng) {
+    constexpr int PER = 16 / sizeof(T);            // table entries per vector
+    const int nvec = ng / PER;
+    const GLOBAL_AS u32x4 *src = (const GLOBAL_AS u32x4 *)tab;
+    const GLOBAL_AS T *gtab = (const GLOBAL_AS T *)tab;
+    T lo = T(0), hi = T(0);
+    if (threadIdx.x == 0) {
+        lo = gtab[ng - 1];
+        hi = gtab[0];
+    }
+    for (int base = 0; base < nvec; base += BLOCK * kTableRound) {
+        u32x4 buf[kTableRound];
+#pragma unroll
+        for (int k = 0; k < kTableRound; ++k) {
+            const int i = base + k * BLOCK + (int)threadIdx.x;
+            if (i < nvec) buf[k] = src[i];
+        }
+#pragma unroll
+        for (int k = 0; k < kTableRound; ++k) {
+            const int i = base + k * BLOCK + (int)threadIdx.x;
+            if (i < nvec) {
+                T vals[PER];
+                __builtin_memcpy(vals, &buf[k], 16);
+#pragma unroll
+                for (int e = 0; e < PER; ++e) Et[1 + i * PER + e] = vals[e];
+            }
+        }
+    }
+    for (int g = nvec * PER + (int)threadIdx.x; g < ng; g += BLOCK) Et[g + 1] = gtab[g];
+    if (threadIdx.x == 0) {
+        Et[0] = lo;
+        Et[ng + 1] = hi;
+    }
+}
+
 // Issue the loads of one block: UNROLL vectors of VEC particles per lane,
 // lane-contiguous so each load instruction covers 64*VEC particles.
 template <typename V, int VEC, int UNROLL>
@@ -234,14 +279,7 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
     double *part = R->tile_part;
     const T ngf = (T)ng;
     const T hi = ngf + T(0.5);
-    if (PUSH && load_table) {
-        const T *tab = gather_table<T>(R);
-        for (int g = threadIdx.x; g < ng; g += BLOCK) Et[g + 1] = tab[g];
-        if (threadIdx.x == 0) {
-            Et[0] = tab[ng - 1];
-            Et[ng + 1] = tab[0];
-        }
-    }
+    if (PUSH && load_table) fill_table<T, BLOCK>(gather_table<T>(R), Et, ng);
     if (threadIdx.x == 0) *next_tile = tb;
     __syncthreads();
     const int lane = threadIdx.x & 63;
