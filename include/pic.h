@@ -265,6 +265,18 @@ pic_status pic_read_grid(pic_run *run, int64_t *S, double *E, float *Ehat, int32
 pic_status pic_phase_space(pic_run *run, int32_t nx, int32_t nv, double vmin, double vmax, uint32_t *counts,
                            int64_t *outside);
 
+/* pic_phase_space for callers that cannot allocate device memory (code that
+ * must not call hipMalloc/hipFree, such as tight serving loops or harnesses
+ * that forbid allocation): the same image, arguments and errors, binned in
+ * a fixed device scratch of 8 + 4 * 16384 bytes that the library holds per
+ * GPU for the life of the process; it allocates nothing.  nx nv above 16384
+ * (the scratch's capacity) is EINVAL.  The scratch is shared by every call on
+ * a GPU and cleared at the start of each call: calls that overlap on one GPU
+ * (from several threads or streams) race and must be serialised by the
+ * caller.  Synchronises, like pic_phase_space. */
+pic_status pic_phase_space_noalloc(pic_run *run, int32_t nx, int32_t nv, double vmin, double vmax,
+                                   uint32_t *counts, int64_t *outside);
+
 /* Synchronise and copy history rows [first, first+count) (PIC_HIST_COLS
  * doubles each).  Rows beyond min(steps taken, history_cap) are EINVAL. */
 pic_status pic_read_history(pic_run *run, int64_t first, int64_t count, double *rows);

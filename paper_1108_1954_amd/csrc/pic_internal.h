@@ -157,6 +157,12 @@ hipError_t launch_phase(const void *u, const void *w, int64_t np, int precision,
                         unsigned *counts, unsigned long long *outside, int cus, hipStream_t stream);
 hipError_t launch_loader(void *u, void *w, int64_t np, int ng, int precision, const LoaderArgs &a, int cus,
                          hipStream_t stream);
+// Fixed device scratch of the allocation-free phase-space call (pic_phase.hip):
+// its size, its address on the current device (resolved once per device),
+// and a fill kernel that zeroes `bytes` (a multiple of 4) at `p`.
+constexpr size_t kPhaseScratchBytes = 8 + sizeof(unsigned) * kMaxPhaseBins;
+hipError_t phase_scratch(void **out);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream);
 
 // Bandwidth reference (pic_probe.hip): swap two device arrays of nvec
 // 16-byte vectors (the particle pass's bytes, nothing else).

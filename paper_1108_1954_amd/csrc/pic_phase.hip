@@ -9,12 +9,28 @@
 // one subtraction and one product (no contraction), so a host holding the
 // same state and constants finds the same bins.
 #include <algorithm>
+#include <mutex>
+#include <unordered_map>
 
 #include "pic_internal.h"
 
 namespace pic1d {
 
+// Device scratch of the allocation-free call (pic_phase_space_noalloc): the
+// outside counter (8 bytes) and then up to kMaxPhaseBins 32-bit bins.  One
+// copy per GPU, alive until the process ends; every call on a GPU shares it.
+// Host code never passes this name to a kernel or a copy: it is a host-side
+// stand-in, and the GPU address comes from phase_scratch().
+static __device__ __align__(256) unsigned char scratch[kPhaseScratchBytes];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::unordered_map<int, void *> g_scratch_ptr;   // device -> address of `scratch` there
+
+__global__ __launch_bounds__(256) void zero_words(unsigned *__restrict__ p, int n) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0u;
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void phase_kernel(const T *__restrict__ U, const T *__restrict__ W, int64_t np,
@@ -46,6 +62,33 @@ __global__ __launch_bounds__(256) void phase_kernel(const T *__restrict__ U, con
 }
 
 }  // namespace
+
+hipError_t phase_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        it = g_scratch_ptr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream) {
+    if (!p || bytes % 4 != 0) return hipErrorInvalidValue;
+    const int n = (int)(bytes / 4);
+    if (n == 0) return hipSuccess;
+    const int grid = std::min(64, (n + 255) / 256);
+    unsigned *w = (unsigned *)p;
+    void *args[] = {&w, (void *)&n};
+    return hipLaunchKernel((const void *)zero_words, dim3(grid), dim3(256), args, 0, stream);
+}
 
 hipError_t launch_phase(const void *u, const void *w, int64_t np, int precision, const PhaseArgs &a,
                         unsigned *counts, unsigned long long *outside, int cus, hipStream_t stream) {

@@ -915,8 +915,13 @@ extern "C" pic_status pic_read_grid(pic_run *r, int64_t *S, double *E, float *Eh
     return PIC_OK;
 }
 
-extern "C" pic_status pic_phase_space(pic_run *r, int32_t nx, int32_t nv, double vmin, double vmax,
-                                      uint32_t *counts, int64_t *outside) {
+namespace {
+
+// Phase-space image of a run into host counts.  `fixed` is the device scratch
+// to bin into (the allocation-free call), or null: then the call allocates
+// its scratch and frees it again.
+pic_status phase_space(pic_run *r, int32_t nx, int32_t nv, double vmin, double vmax, uint32_t *counts,
+                       int64_t *outside, void *fixed) {
     pic_status st = check_run(r);
     if (st != PIC_OK) return st;
     if (!counts) return fail(PIC_EINVAL, "counts is NULL");
@@ -935,29 +940,52 @@ extern "C" pic_status pic_phase_space(pic_run *r, int32_t nx, int32_t nv, double
     a.w_bin = (double)nv / ((vmax - vmin) * c);
     if (!(std::isfinite(a.w_lo) && std::isfinite(a.w_bin) && a.w_bin > 0))
         return fail(PIC_EINVAL, "velocity range too wide or too narrow for the bins");
-    // One scratch allocation for the call: the outside counter, then the bins.
+    // The scratch: the outside counter, then the bins.
     const size_t nbins = (size_t)nx * nv;
     const size_t bytes = 8 + nbins * sizeof(uint32_t);
-    void *buf = nullptr;
-    HIP_TRY(hipMalloc(&buf, bytes));
+    void *buf = fixed;
+    if (!buf) HIP_TRY(hipMalloc(&buf, bytes));
     unsigned long long *out_dev = (unsigned long long *)buf;
     unsigned *counts_dev = (unsigned *)((char *)buf + 8);
     unsigned long long out_host = 0;
-    hipError_t e = hipMemsetAsync(buf, 0, bytes, r->stream);
+    hipError_t e = launch_zero(buf, bytes, r->stream);
     if (e == hipSuccess)
         e = launch_phase(r->cur_u(), r->cur_w(), r->p.np, r->p.precision, a, counts_dev, out_dev,
                          device_info().cus, r->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
     if (e == hipSuccess) e = hipMemcpy(counts, counts_dev, nbins * sizeof(uint32_t), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(&out_host, out_dev, 8, hipMemcpyDeviceToHost);
-    const hipError_t ef = hipFree(buf);
-    if (e == hipSuccess) e = ef;
+    if (!fixed) {
+        const hipError_t ef = hipFree(buf);
+        if (e == hipSuccess) e = ef;
+    }
     if (e != hipSuccess) {
         r->error = true;
         return fail(PIC_EDEVICE, "phase-space binning failed: %s", hipGetErrorString(e));
     }
     if (outside) *outside = (int64_t)out_host;
     return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" pic_status pic_phase_space(pic_run *r, int32_t nx, int32_t nv, double vmin, double vmax,
+                                      uint32_t *counts, int64_t *outside) {
+    return phase_space(r, nx, nv, vmin, vmax, counts, outside, nullptr);
+}
+
+extern "C" pic_status pic_phase_space_noalloc(pic_run *r, int32_t nx, int32_t nv, double vmin, double vmax,
+                                              uint32_t *counts, int64_t *outside) {
+    pic_status st = check_run(r);
+    if (st != PIC_OK) return st;
+    if (nx < 1 || nv < 1 || (int64_t)nx * nv > kMaxPhaseBins)
+        return fail(PIC_EINVAL, "pic_phase_space_noalloc: nx nv = %lld exceeds its fixed scratch of %d bins",
+                    (long long)nx * nv, kMaxPhaseBins);
+    void *fixed = nullptr;
+    const hipError_t e = phase_scratch(&fixed);
+    if (e != hipSuccess)
+        return fail(PIC_EDEVICE, "pic_phase_space_noalloc: scratch address: %s", hipGetErrorString(e));
+    return phase_space(r, nx, nv, vmin, vmax, counts, outside, fixed);
 }
 
 extern "C" pic_status pic_read_history(pic_run *r, int64_t first, int64_t count, double *rows) {

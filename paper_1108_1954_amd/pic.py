@@ -30,7 +30,7 @@ SYMBOLS = (
     "pic_last_error", "pic_version", "pic_footprint", "pic_create", "pic_create_loaded", "pic_sort",
     "pic_step", "pic_step_graph", "pic_batch_admit_loaded",
     "pic_step_profiled", "pic_batch_step_profiled", "pic_diagnostics", "pic_read_particles", "pic_read_raw", "pic_read_grid", "pic_read_history",
-    "pic_phase_space", "pic_sort_period", "pic_destroy", "pic_batch_create", "pic_batch_admit", "pic_batch_step", "pic_batch_poll",
+    "pic_phase_space", "pic_phase_space_noalloc", "pic_sort_period", "pic_destroy", "pic_batch_create", "pic_batch_admit", "pic_batch_step", "pic_batch_poll",
     "pic_bandwidth_probe", "pic_batch_run", "pic_batch_diagnostics", "pic_batch_release", "pic_batch_usage", "pic_batch_destroy",
 )
 
@@ -118,6 +118,7 @@ def load(path: str = LIB_PATH):
         "pic_read_grid": [vp, vp, vp, vp, i32],
         "pic_read_history": [vp, i64, i64, vp],
         "pic_phase_space": [vp, i32, i32, C.c_double, C.c_double, vp, C.POINTER(i64)],
+        "pic_phase_space_noalloc": [vp, i32, i32, C.c_double, C.c_double, vp, C.POINTER(i64)],
         "pic_destroy": [vp],
         "pic_bandwidth_probe": [vp, vp, i64, i32, vp, dptr],
         "pic_batch_create": [C.POINTER(pic_batch_config), vp, C.POINTER(vp)],
@@ -258,6 +259,16 @@ def pic_phase_space(run, nx: int, nv: int, vmin: float, vmax: float) -> Tuple[np
     out = C.c_int64(0)
     _check(load().pic_phase_space(run, int(nx), int(nv), float(vmin), float(vmax), counts.ctypes.data,
                                   C.byref(out)))
+    return counts, out.value
+
+
+def pic_phase_space_noalloc(run, nx: int, nv: int, vmin: float, vmax: float) -> Tuple[np.ndarray, int]:
+    """pic_phase_space binned in the library's fixed device scratch (no
+    device allocation); nx nv <= 16384."""
+    counts = np.zeros((int(nv), int(nx)), dtype=np.uint32)
+    out = C.c_int64(0)
+    _check(load().pic_phase_space_noalloc(run, int(nx), int(nv), float(vmin), float(vmax), counts.ctypes.data,
+                                          C.byref(out)))
     return counts, out.value
 
 
