@@ -205,12 +205,28 @@ __device__ __forceinline__ double wave_sum(double v) {
     return ((lane_read(v, 0) + lane_read(v, 16)) + lane_read(v, 32)) + lane_read(v, 48);
 }
 
-// Integer sum over the 64 lanes (exact in any order).  Both overloads live
-// here so that no scope hides one of them from a caller of the other.
+// Integer sum over the 64 lanes (exact in any order), with the same DPP
+// moves of the two 32-bit halves (data movement only) and the same lane
+// reads.  Both overloads live here so that no scope hides one of them from a
+// caller of the other.
+template <int CTRL>
+__device__ __forceinline__ long long dpp_move(long long v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(unsigned long long)v, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)((unsigned long long)v >> 32), CTRL, 0xf, 0xf,
+                                               false);
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ long long lane_read(long long v, int lane) {
+    const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)(unsigned long long)v, lane);
+    const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)v >> 32), lane);
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
 __device__ __forceinline__ long long wave_sum(long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x141>(v);
+    v += dpp_move<0x140>(v);
+    return ((lane_read(v, 0) + lane_read(v, 16)) + lane_read(v, 32)) + lane_read(v, 48);
 }
 
 

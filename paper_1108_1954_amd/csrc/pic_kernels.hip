@@ -277,6 +277,7 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
     T *U = (T *)R->u;
     T *W = (T *)R->w;
     double *part = R->tile_part;
+    unsigned long long *S = R->S;                    // read now: later the pass's stores could alias it
     const T ngf = (T)ng;
     const T hi = ngf + T(0.5);
     if (PUSH && load_table) fill_table<T, BLOCK>(gather_table<T>(R), Et, ng);
@@ -366,7 +367,6 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
     // the two ghost nodes.  No fence: the solve runs in the next launch, after
     // the kernel boundary has made every merge visible.  Starting at a
     // chunk-dependent rotation spreads concurrent merges over addresses.
-    unsigned long long *S = R->S;
     const int rot = (int)(((unsigned)chunk * 97u) % (unsigned)ng);
     for (int k = threadIdx.x; k < ng; k += BLOCK) {
         int c = k + rot;

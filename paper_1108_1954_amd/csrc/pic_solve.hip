@@ -36,52 +36,12 @@ __host__ __device__ __forceinline__ int solve_threads(int ng) {
 // after every read of this one.  `par` selects the buffer and must follow
 // the same sequence in every thread.
 constexpr int kRedSlots = kMaxSolveThreads / 64;
+constexpr int kSolvePer = 8;     // nodes per thread at most: ng <= 8 solve_threads(ng)
+constexpr int kPartBatch = 8;    // tile partials per thread loaded with the nodes
 
 // Sum over the first nthr threads in a fixed order (butterfly inside each
 // wavefront, then wavefront totals in index order); every thread gets the
 // value.  All threads of the block must call it.
-template <typename V>
-__device__ V solve_sum(V v, V *red2, int &par, int nthr) {
-    V *red = red2 + kRedSlots * par;
-    par ^= 1;
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && (int)threadIdx.x < nthr) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    V s = 0;
-    for (int k = 0; k < nthr / 64; ++k) s += red[k];
-    return s;
-}
-
-// Exclusive prefix sum over the first nthr threads in index order.
-__device__ double solve_exclusive_scan(double v, double *red2, int &par, int nthr) {
-    double *red = red2 + kRedSlots * par;
-    par ^= 1;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double inc = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        double t = __shfl_up(inc, o);
-        if (lane >= o) inc += t;
-    }
-    double exc = __shfl_up(inc, 1);
-    if (lane == 0) exc = 0.0;
-    if (lane == 63 && (int)threadIdx.x < nthr) red[wv] = inc;
-    __syncthreads();
-    double off = 0.0;
-    for (int k = 0; k < wv && k < nthr / 64; ++k) off += red[k];
-    return off + exc;
-}
-
-// The paper's field solver (Sec. 2.2, Sec. 3.3): matrix-free conjugate
-// gradient on the three-point system with the potential at node 0 held at
-// zero (its row is the identity, its residual zero), started from zero and
-// run for a fixed number of iterations, then the central-difference field.
-// Each thread owns up to kCgPer strided nodes and keeps their potential,
-// residual and A d in registers; the dot products are sums in a fixed
-// order.  On entry D[g] holds S_g; on exit D[g] holds E_g.
-constexpr int kCgPer = 8;   // nodes per thread: ng <= 8 solve_threads(ng)
-constexpr int kCgWaveMaxNg = 64 * kCgPer;   // grids one wavefront solves alone
-
 // v of lane i - 1 (lane 0: fill) and of lane i + 1 (lane 63: fill).
 __device__ __forceinline__ double lane_prev(double v, double fill) {
     const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), 0x138, 0xf, 0xf, false);
@@ -93,6 +53,135 @@ __device__ __forceinline__ double lane_next(double v, double fill) {
     const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), 0x130, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);
 }
+
+// The first `nw` wavefront totals of a reduction, summed in slot order.
+// Slots are read four at a time (one LDS round trip per four; slots past nw
+// are read but not added), then added in order.
+template <typename V>
+__device__ __forceinline__ V sum_slots(const V *red, int nw) {
+    V s = 0;
+#pragma unroll
+    for (int k0 = 0; k0 < kRedSlots; k0 += 4) {
+        if (k0 < nw) {
+            V vals[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) vals[k] = red[k0 + k];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k0 + k < nw) s += vals[k];
+        }
+    }
+    return s;
+}
+
+template <typename V>
+__device__ V solve_sum(V v, V *red2, int &par, int nthr) {
+    V *red = red2 + kRedSlots * par;
+    par ^= 1;
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && (int)threadIdx.x < nthr) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return sum_slots(red, nthr >> 6);
+}
+
+// The exact integer sum of `ti` and the sums of `a` and `b` over the first
+// nthr threads, each in the order of solve_sum, with a single barrier: the
+// wavefront totals go to slots of their own (ti_red, ab_red), which no other
+// reduction of the solve uses.  Every thread gets the three values.
+__device__ void solve_sum3(long long &ti, double &a, double &b, long long *ti_red, double *ab_red, int nthr) {
+    const long long wt = wave_sum(ti);
+    const double wa = wave_sum(a), wb = wave_sum(b);
+    if ((threadIdx.x & 63) == 0 && (int)threadIdx.x < nthr) {
+        ti_red[threadIdx.x >> 6] = wt;
+        ab_red[threadIdx.x >> 6] = wa;
+        ab_red[kRedSlots + (threadIdx.x >> 6)] = wb;
+    }
+    __syncthreads();
+    ti = sum_slots(ti_red, nthr >> 6);
+    a = sum_slots(ab_red, nthr >> 6);
+    b = sum_slots(ab_red + kRedSlots, nthr >> 6);
+}
+
+// Exclusive prefix sum over the first nthr threads in index order.  Inside a
+// wavefront: an inclusive scan of each row of 16 lanes by DPP row shifts
+// (1, 2, 4, 8; lanes shifted in from outside the row add zero), then the
+// totals of rows 0 and 2 broadcast into rows 1 and 3 and the total of
+// rows 0-1 into rows 2-3 (DPP row broadcasts), then a shift by one lane.
+// Then the wavefront totals (lane 63) of lower wavefronts, in order.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_scan_term(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ double solve_exclusive_scan(double v, double *red2, int &par, int nthr) {
+    double *red = red2 + kRedSlots * par;
+    par ^= 1;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double inc = v;
+    inc += dpp_scan_term<0x111, 0xf>(inc);     // row_shr:1
+    inc += dpp_scan_term<0x112, 0xf>(inc);     // row_shr:2
+    inc += dpp_scan_term<0x114, 0xf>(inc);     // row_shr:4
+    inc += dpp_scan_term<0x118, 0xf>(inc);     // row_shr:8
+    inc += dpp_scan_term<0x142, 0xa>(inc);     // row_bcast:15 into rows 1 and 3
+    inc += dpp_scan_term<0x143, 0xc>(inc);     // row_bcast:31 into rows 2 and 3
+    double exc = lane_prev(inc, 0.0);          // wave_shr:1, lane 0 gets 0
+    if (lane == 63 && (int)threadIdx.x < nthr) red[wv] = inc;
+    __syncthreads();
+    const double off = sum_slots(red, min(wv, nthr / 64));
+    return off + exc;
+}
+
+// The descriptor fields the solve reads, loaded together at its start.  A
+// field read after the solve's first global store would be a fresh memory
+// round trip (the store might alias the descriptor, so the compiler cannot
+// keep it in a register); taken by value here they cost one.
+struct SolveView {
+    unsigned long long *S, *S_last;
+    float *Ehat;
+    double *Ehat64, *E64, *hist;
+    const double *tile_part;
+    int64_t step, step_target, hist_cap;
+    double dx, qfac, ecoef, kcoef, pcoef, kinetic_now, field_now;
+    int ng, ntiles, solver, cg_iters;
+};
+
+__device__ __forceinline__ SolveView solve_view(const RunDev *R) {
+    SolveView v;
+    v.S = R->S;
+    v.S_last = R->S_last;
+    v.Ehat = R->Ehat;
+    v.Ehat64 = R->Ehat64;
+    v.E64 = R->E64;
+    v.hist = R->hist;
+    v.tile_part = R->tile_part;
+    v.step = R->step;
+    v.step_target = R->step_target;
+    v.hist_cap = R->hist_cap;
+    v.dx = R->dx;
+    v.qfac = R->qfac;
+    v.ecoef = R->ecoef;
+    v.kcoef = R->kcoef;
+    v.pcoef = R->pcoef;
+    v.kinetic_now = R->kinetic_now;
+    v.field_now = R->field_now;
+    v.ng = R->ng;
+    v.ntiles = R->ntiles;
+    v.solver = R->solver;
+    v.cg_iters = R->cg_iters;
+    return v;
+}
+
+// The paper's field solver (Sec. 2.2, Sec. 3.3): matrix-free conjugate
+// gradient on the three-point system with the potential at node 0 held at
+// zero (its row is the identity, its residual zero), started from zero and
+// run for a fixed number of iterations, then the central-difference field.
+// Each thread owns up to kCgPer strided nodes and keeps their potential,
+// residual and A d in registers; the dot products are sums in a fixed
+// order.  On entry D[g] holds S_g; on exit D[g] holds E_g.
+constexpr int kCgPer = 8;   // nodes per thread: ng <= 8 solve_threads(ng)
+constexpr int kCgWaveMaxNg = 64 * kCgPer;   // grids one wavefront solves alone
 
 // One node's row of the CG system applied to d: the identity at node 0,
 // d_{g-1} - 2 d_g + d_{g+1} elsewhere, with d_ng = 0 beyond the last node.
@@ -108,9 +197,9 @@ __device__ __forceinline__ double cg_next_d(double beta, double d, double r) { r
 // The CG on one wavefront, for ng <= 512: lane l owns nodes l, l + 64, ...;
 // the neighbours across the ends of a row of 64 nodes come from lanes 63
 // and 0 of the adjacent rows (readlane), so no LDS or barrier is needed.
-__device__ __forceinline__ void cg_paper_wave(RunDev *R, double *D, double meanS) {
-    const int ng = R->ng, lane = threadIdx.x & 63;
-    const double dx = R->dx, qf = R->qfac;
+__device__ __forceinline__ void cg_paper_wave(const SolveView &V, double *D, double meanS) {
+    const int ng = V.ng, lane = threadIdx.x & 63;
+    const double dx = V.dx, qf = V.qfac;
     double ph[kCgPer], r[kCgPer], d[kCgPer];
     double rr = 0.0;
 #pragma unroll
@@ -124,7 +213,7 @@ __device__ __forceinline__ void cg_paper_wave(RunDev *R, double *D, double meanS
     rr = wave_sum(rr);
     const int rows = (ng + 63) >> 6;                   // rows of 64 nodes that hold nodes
     if (__builtin_sqrt(rr) > 1e-16) {
-        const int iters = R->cg_iters;
+        const int iters = V.cg_iters;
         for (int it = 0; it < iters; ++it) {
             double z[kCgPer];
             double zd = 0.0;
@@ -196,15 +285,16 @@ __device__ __forceinline__ void cg_paper_wave(RunDev *R, double *D, double meanS
 // and the two dot products).  Keeping d in registers as well, with DPP
 // shifts inside a wavefront and an LDS exchange at its ends, measured
 // slower here (12-22% at ng 2048-8192) than these conflict-free LDS reads.
-__device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, int &par, double meanS, int nthr) {
-    if (R->ng <= kCgWaveMaxNg) {
-        if (threadIdx.x < 64) cg_paper_wave(R, D, meanS);
+__device__ __forceinline__ void cg_paper(const SolveView &V, double *D, double *red, int &par, double meanS,
+                                         int nthr) {
+    if (V.ng <= kCgWaveMaxNg) {
+        if (threadIdx.x < 64) cg_paper_wave(V, D, meanS);
         __syncthreads();                              // D: E_g, for every wavefront
         return;
     }
-    const int ng = R->ng, tid = threadIdx.x;
+    const int ng = V.ng, tid = threadIdx.x;
     const bool worker = tid < nthr;
-    const double dx = R->dx, qf = R->qfac;
+    const double dx = V.dx, qf = V.qfac;
     double ph[kCgPer], r[kCgPer], z[kCgPer];
     double rr = 0.0;
 #pragma unroll
@@ -224,7 +314,7 @@ __device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, int 
     }
     rr = solve_sum(rr, red, par, nthr);                          // syncs: d complete
     if (__builtin_sqrt(rr) > 1e-16) {
-        const int iters = R->cg_iters;
+        const int iters = V.cg_iters;
         for (int it = 0; it < iters; ++it) {
             double zd = 0.0;
 #pragma unroll
@@ -304,71 +394,79 @@ __device__ __forceinline__ void cg_paper(RunDev *R, double *D, double *red, int 
 constexpr int kSolveLds = kMaxNg + kMaxNg / 8;
 __device__ __forceinline__ int dpad(int g) { return g + (g >> 3); }
 
-__device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, long long *redi,
-                                       bool prologue) {
-    const int ng = R->ng;
+__device__ __forceinline__ void solve_run(RunDev *R, const SolveView &V, double *D, double *red, long long *redi,
+                                          double *red3, bool prologue) {
+    const int ng = V.ng;
     const int tid = threadIdx.x;
     const int nthr = solve_threads(ng);
     const bool worker = tid < nthr;
-    int par = 0, pari = 0;                         // reduction buffers (see solve_sum)
-    unsigned long long *S = R->S;
-    unsigned long long *S_last = R->S_last;
+    int par = 0;                                   // reduction buffers (see solve_sum)
+    unsigned long long *S = V.S;
+    unsigned long long *S_last = V.S_last;
+    const bool cg = V.solver == 1;
+    const double *part = V.tile_part;
+    const int ntiles = V.ntiles;
     // Plain loads: this runs in the launch after the deposit, so the kernel
     // boundary orders them after every workgroup's merge into S and its tile
-    // partials.
-    // Loads are issued in batches of kBatch so that many are in flight; the
-    // sums keep the strided order g = tid, tid + 256, ...
-    constexpr int kBatch = 16;
+    // partials.  Every thread owns at most kSolvePer nodes (g = tid + k nthr,
+    // see solve_threads), and the loads of all of them and of the first
+    // kPartBatch tile partials (t = tid + k nthr) are issued before any is
+    // used: one memory round trip for the solve's inputs.  The sums keep the
+    // strided order g (t) = tid, tid + nthr, ...
+    unsigned long long sv[kSolvePer];
+    f64x2 pv[kPartBatch];
+#pragma unroll
+    for (int k = 0; k < kSolvePer; ++k) {
+        const int g = tid + k * nthr;
+        sv[k] = worker && g < ng ? S[g] : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < kPartBatch; ++k) {
+        const int t = tid + k * nthr;
+        pv[k] = worker && t < ntiles ? *reinterpret_cast<const f64x2 *>(part + kPartCols * t) : f64x2{0.0, 0.0};
+    }
     long long tot = 0;
-    const bool cg = R->solver == 1;
-    if (worker) {
-        for (int g0 = tid; g0 < ng; g0 += nthr * kBatch) {
-            unsigned long long sv[kBatch];
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                const int g = g0 + k * nthr;
-                sv[k] = g < ng ? S[g] : 0ull;
-            }
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                const int g = g0 + k * nthr;
-                if (g < ng) {
-                    S[g] = 0ull;
-                    S_last[g] = sv[k];
-                    tot += (long long)sv[k];
-                    D[cg ? g : dpad(g)] = (double)sv[k];
-                }
-            }
+    for (int k = 0; k < kSolvePer; ++k) {
+        const int g = tid + k * nthr;
+        if (worker && g < ng) {
+            S[g] = 0ull;
+            S_last[g] = sv[k];
+            tot += (long long)sv[k];
+            D[cg ? g : dpad(g)] = (double)sv[k];
         }
     }
-    // tile partials of the diagnostics: loaded now, summed in the same
-    // strided order, so their latency overlaps the solve
+    // tile partials of the diagnostics, then any beyond the first batch
     double a1 = 0.0, a2 = 0.0;
-    const double *part = R->tile_part;
-    const int ntiles = R->ntiles;
-    if (worker) {
-        for (int t0 = tid; t0 < ntiles; t0 += nthr * kBatch) {
-            f64x2 pv[kBatch];
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
+    for (int k = 0; k < kPartBatch; ++k) {
+        a1 += pv[k].x;
+        a2 += pv[k].y;
+    }
+    if (worker) {
+        for (int t0 = tid + kPartBatch * nthr; t0 < ntiles; t0 += nthr * kPartBatch) {
+#pragma unroll
+            for (int k = 0; k < kPartBatch; ++k) {
                 const int t = t0 + k * nthr;
                 pv[k] = t < ntiles ? *reinterpret_cast<const f64x2 *>(part + kPartCols * t) : f64x2{0.0, 0.0};
             }
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
+            for (int k = 0; k < kPartBatch; ++k) {
                 a1 += pv[k].x;
                 a2 += pv[k].y;
             }
         }
     }
-    tot = solve_sum(tot, redi, pari, nthr);                   // exact: sum_g S_g
+    // the three sums in one block reduction (and the barrier after which D
+    // holds every S_g): exact sum_g S_g and the two diagnostics sums
+    solve_sum3(tot, a1, a2, redi, red3, nthr);
     const double meanS = (double)tot / (double)ng;
     double C = 0.0;
     if (cg) {
         __syncthreads();                          // D holds every S_g
-        cg_paper(R, D, red, par, meanS, nthr);               // D: E_g
+        cg_paper(V, D, red, par, meanS, nthr);               // D: E_g
     } else {
-        const double scale = R->qfac * R->dx;     // face-field change per unit of S
+        const double scale = V.qfac * V.dx;       // face-field change per unit of S
         const int seg = (ng + nthr - 1) / nthr;
         const int g0 = worker ? min(tid * seg, ng) : ng, g1 = min(g0 + seg, ng);
         double acc = 0.0;
@@ -385,10 +483,10 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
         }
         C = -solve_sum(csum, red, par, nthr) / (double)ng;   // syncs: D complete
     }
-    const double ecoef = R->ecoef;
-    float *Ehat = R->Ehat;
-    double *Ehat64 = R->Ehat64;
-    double *E64 = R->E64;
+    const double ecoef = V.ecoef;
+    float *Ehat = V.Ehat;
+    double *Ehat64 = V.Ehat64;
+    double *E64 = V.E64;
     double we = 0.0;
     if (worker) {
         for (int g = tid; g < ng; g += nthr) {
@@ -406,18 +504,16 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
             we += E * E;
         }
     }
-    we = 0.5 * R->dx * solve_sum(we, red, par, nthr);
-    a1 = solve_sum(a1, red, par, nthr);
-    a2 = solve_sum(a2, red, par, nthr);
+    we = 0.5 * V.dx * solve_sum(we, red, par, nthr);
     if (tid == 0) {
-        const double kc = R->kcoef, pc = R->pcoef;
+        const double kc = V.kcoef, pc = V.pcoef;
         const double k_new = kc * a1;
         if (!prologue) {
-            const int64_t n = R->step;
-            if (n < R->hist_cap) {
-                double *row = R->hist + (size_t)kHistCols * (size_t)n;
-                row[0] = 0.5 * (R->kinetic_now + k_new);   // KE^n, time-centred
-                row[1] = R->field_now;                     // W_E^n of the gathered field
+            const int64_t n = V.step;
+            if (n < V.hist_cap) {
+                double *row = V.hist + (size_t)kHistCols * (size_t)n;
+                row[0] = 0.5 * (V.kinetic_now + k_new);    // KE^n, time-centred
+                row[1] = V.field_now;                      // W_E^n of the gathered field
                 row[2] = pc * a2;                          // P^{n+1/2}
                 row[3] = k_new;                            // K^{n+1/2}
             }
@@ -435,10 +531,12 @@ __device__ __forceinline__ void solve_run(RunDev *R, double *D, double *red, lon
 __global__ __launch_bounds__(kMaxSolveThreads) void solve_kernel(RunDev *runs, int prologue) {
     __shared__ double D[kSolveLds];
     __shared__ double red[2 * kRedSlots];
-    __shared__ long long redi[2 * kRedSlots];
+    __shared__ long long redi[kRedSlots];
+    __shared__ double red3[2 * kRedSlots];
     RunDev *R = runs + blockIdx.x;
-    if (!prologue && R->step >= R->step_target) return;
-    solve_run(R, D, red, redi, prologue != 0);
+    const SolveView V = solve_view(R);
+    if (!prologue && V.step >= V.step_target) return;
+    solve_run(R, V, D, red, redi, red3, prologue != 0);
 }
 
 }  // namespace
