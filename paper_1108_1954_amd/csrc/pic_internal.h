@@ -88,8 +88,9 @@ struct LaunchShape {
 //   items == nullptr: single run `runs[0]`, tiles split evenly over `grid`
 //   workgroups.  Otherwise the workgroups take items[0 .. queue->nitems)
 //   through the queue.
-//   The solve launch has nsolve workgroups; workgroup b solves runs[b]
-//   (idle and finished runs return at once).
+//   The solve launch has nsolve workgroups; workgroup b solves
+//   runs[slots[b]] (slots == nullptr: runs[b]); a slot of -1, idle and
+//   finished runs return at once.
 //   prologue != 0: deposit + solve only (creation), no push.
 //   ev (optional): events recorded before the particle pass (e0), between
 //   the two launches (e1) and after the solve (e2).
@@ -98,11 +99,13 @@ struct StepEvents {
 };
 hipError_t launch_step(RunDev *runs, const WorkItem *items, WorkQueue *queue,
                        int grid, const LaunchShape &shape, int ng_lds, int precision, int prologue,
-                       int nsolve, hipStream_t stream, const StepEvents *ev = nullptr);
+                       const int32_t *slots, int nsolve, hipStream_t stream, const StepEvents *ev = nullptr);
 
 // The solve launch alone (pic_solve.hip): nsolve workgroups, workgroup b
-// solves runs[b]; ng_max bounds the ng of every run in the launch.
-hipError_t launch_solve(RunDev *runs, int nsolve, int prologue, int ng_max, hipStream_t stream);
+// solves runs[slots[b]] (or runs[b]); ng_max bounds the ng of every run in
+// the launch.
+hipError_t launch_solve(RunDev *runs, const int32_t *slots, int nsolve, int prologue, int ng_max,
+                        hipStream_t stream);
 
 // The particle pass alone (used by the autotuner on saved state).
 hipError_t launch_particles(RunDev *runs, const WorkItem *items, WorkQueue *queue,
@@ -170,10 +173,12 @@ hipError_t launch_swap(void *a, void *b, int64_t nvec, int cus, hipStream_t stre
 
 // Autotuner (pic_tune.hip).  tune_key names a size class; tune_lookup finds
 // a cached shape; tune_shapes times `launch(shape)` (one particle pass on
-// saved state) for every candidate and caches and returns the fastest.
+// saved state, after an untimed `prepare(shape)`) for every candidate and
+// caches and returns the choice; *best holds the incumbent on entry.
 std::string tune_key(const char *kind, int precision, int ng, int64_t np);
 bool tune_lookup(const std::string &key, LaunchShape *out);
 hipError_t tune_shapes(const std::string &key, int precision, hipStream_t stream,
+                       const std::function<hipError_t(const LaunchShape &)> &prepare,
                        const std::function<hipError_t(const LaunchShape &)> &launch, LaunchShape *best);
 
 // ---------------------------------------------- wavefront FP64 sums --

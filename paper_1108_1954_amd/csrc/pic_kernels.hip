@@ -510,15 +510,15 @@ hipError_t launch_particles(RunDev *runs, const WorkItem *items, WorkQueue *queu
 }
 
 hipError_t launch_step(RunDev *runs, const WorkItem *items, WorkQueue *queue, int grid,
-                       const LaunchShape &ls, int ng_lds, int precision, int prologue, int nsolve,
-                       hipStream_t stream, const StepEvents *ev) {
+                       const LaunchShape &ls, int ng_lds, int precision, int prologue, const int32_t *slots,
+                       int nsolve, hipStream_t stream, const StepEvents *ev) {
     if (nsolve <= 0) return hipErrorInvalidValue;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev->e0, stream)) != hipSuccess) return e;
     e = launch_particles(runs, items, queue, grid, ls, ng_lds, precision, prologue, stream);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev->e1, stream)) != hipSuccess) return e;
-    e = launch_solve(runs, nsolve, prologue, ng_lds, stream);
+    e = launch_solve(runs, slots, nsolve, prologue, ng_lds, stream);
     if (e != hipSuccess) return e;
     if (ev) return hipEventRecord(ev->e2, stream);
     return hipSuccess;

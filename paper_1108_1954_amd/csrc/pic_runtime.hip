@@ -350,7 +350,7 @@ pic_status queue_device_init(pic_run *r, const RunDev *desc) {
     HIP_TRY(hipMemsetAsync(r->host.tile_part, 0, (size_t)r->lay.ntiles * kPartCols * 8, r->stream));
     HIP_TRY(hipMemcpyAsync(r->dev, desc, sizeof(RunDev), hipMemcpyHostToDevice, r->stream));
     HIP_TRY(step_prepare(r->shape, r->p.precision));
-    HIP_TRY(launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng, r->p.precision, 1,
+    HIP_TRY(launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng, r->p.precision, 1, nullptr,
                         1, r->stream));
     return PIC_OK;
 }
@@ -408,13 +408,13 @@ pic_status choose_shape(pic_run *r, const DeviceInfo &d) {
             hipError_t te = hipSuccess;
             if (st == PIC_OK) {
                 const int cus = d.cus;
-                te = tune_shapes(key, r->p.precision, r->stream,
-                                 [r, cus](const LaunchShape &s) {
-                                     return launch_particles(r->dev, nullptr, nullptr,
-                                                             single_run_grid(r, s, cus), s, r->p.ng,
-                                                             r->p.precision, 0, r->stream);
-                                 },
-                                 &shape);
+                te = tune_shapes(
+                    key, r->p.precision, r->stream, [](const LaunchShape &) { return hipSuccess; },
+                    [r, cus](const LaunchShape &s) {
+                        return launch_particles(r->dev, nullptr, nullptr, single_run_grid(r, s, cus), s, r->p.ng,
+                                                r->p.precision, 0, r->stream);
+                    },
+                    &shape);
                 st = save_particles(r, tmp, true);
             }
             hipError_t se = hipStreamSynchronize(r->stream);
@@ -654,7 +654,7 @@ pic_status enqueue_step(pic_run *r, const StepEvents *ev = nullptr) {
         if (e == hipSuccess) r->swapped = !r->swapped;
     }
     if (e == hipSuccess)
-        e = launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng, r->p.precision, 0, 1,
+        e = launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng, r->p.precision, 0, nullptr, 1,
                         r->stream, ev);
     if (e != hipSuccess) {
         r->error = true;
@@ -714,7 +714,8 @@ extern "C" pic_status pic_step_graph(pic_run *r, int64_t nsteps, int32_t graph_s
     // steps.  A graph is replayed only where no sort falls inside it.
     const pic_run *rc = r;
     auto step_launch = [rc](hipStream_t s) {
-        return launch_step(rc->dev, nullptr, nullptr, rc->grid, rc->shape, rc->p.ng, rc->p.precision, 0, 1, s);
+        return launch_step(rc->dev, nullptr, nullptr, rc->grid, rc->shape, rc->p.ng, rc->p.precision, 0, nullptr, 1,
+                           s);
     };
     int64_t left = nsteps;
     while (left > 0) {
@@ -1109,6 +1110,12 @@ struct pic_batch {
     WorkQueue *queue_dev = nullptr;   // device work queue of the particle pass
     WorkItem *items_host = nullptr;   // pinned staging
     WorkQueue *queue_host = nullptr;
+    // Slots the solve launch covers: the unfinished members' slots in slot
+    // order, padded with -1 to nsolve, a power of two (so that a captured
+    // graph changes only when that bucket does, not at every arrival).
+    int32_t *slots_dev = nullptr;
+    int32_t *slots_host = nullptr;    // pinned staging
+    int nsolve = 1;
     hipEvent_t staged = nullptr;      // staging buffers free again
     int item_cap = 0;
     int grid = 0, grid_max = 0, cus = 256;
@@ -1184,6 +1191,21 @@ pic_status rebuild_schedule(pic_batch *b) {
         return a.tb < c.tb;
     });
     HIP_TRY(hipEventSynchronize(b->staged));
+    // the solve launch's slot list
+    int nact = 0;
+    for (auto &kv : b->members)
+        if (kv.second.launch_done > b->launches) b->slots_host[nact++] = kv.second.slot;
+    std::sort(b->slots_host, b->slots_host + nact);
+    int bucket = 1;
+    while (bucket < nact) bucket <<= 1;
+    for (int k = nact; k < bucket; ++k) b->slots_host[k] = -1;
+    if (bucket != b->nsolve && b->graph) {             // the captured solve launches have the old grid
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    b->nsolve = bucket;
+    HIP_TRY(hipMemcpyAsync(b->slots_dev, b->slots_host, sizeof(int32_t) * (size_t)bucket, hipMemcpyHostToDevice,
+                           b->stream));
     const int n = (int)chunks.size();
     for (int k = 0; k < n; ++k) {
         const Chunk &c = chunks[(size_t)k];
@@ -1250,7 +1272,7 @@ pic_status ensure_graph(pic_batch *b) {
     return capture_graph(
         [bc](hipStream_t s) {
             return launch_step(bc->table, bc->items_dev, bc->queue_dev, bc->grid, bc->shape,
-                               bc->cfg.ng_max, PIC_FP32, 0, bc->cfg.max_runs, s);
+                               bc->cfg.ng_max, PIC_FP32, 0, bc->slots_dev, bc->nsolve, s);
         },
         b->cfg.graph_steps, &b->graph);
 }
@@ -1366,6 +1388,11 @@ extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream
     ok = ok && hipMalloc((void **)&b->queue_dev, sizeof(WorkQueue)) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&b->items_host, sizeof(WorkItem) * (size_t)b->item_cap) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&b->queue_host, sizeof(WorkQueue)) == hipSuccess;
+    // the slot list is padded to a power of two: room for the next one up
+    size_t slot_cap = 1;
+    while (slot_cap < (size_t)cfg->max_runs) slot_cap <<= 1;
+    ok = ok && hipMalloc((void **)&b->slots_dev, sizeof(int32_t) * slot_cap) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&b->slots_host, sizeof(int32_t) * slot_cap) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&b->idle_host, sizeof(RunDev)) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&b->io_stream, hipStreamNonBlocking) == hipSuccess;
@@ -1563,15 +1590,20 @@ pic_status batch_choose_shape(pic_batch *b) {
         }
         hipError_t te = hipSuccess;
         if (st == PIC_OK) {
-            te = tune_shapes(key, PIC_FP32, b->stream,
-                             [b](const LaunchShape &s) {
-                                 b->shape = s;
-                                 b->grid = b->cus * step_occupancy(s, b->cfg.ng_max, PIC_FP32);
-                                 if (rebuild_schedule(b) != PIC_OK) return hipErrorInvalidValue;
-                                 return launch_particles(b->table, b->items_dev, b->queue_dev, b->grid, s,
-                                                         b->cfg.ng_max, PIC_FP32, 0, b->stream);
-                             },
-                             &shape);
+            // the schedule depends on the shape (grid and chunk sizes): it is
+            // rebuilt before each timed launch, outside the timing
+            te = tune_shapes(
+                key, PIC_FP32, b->stream,
+                [b](const LaunchShape &s) {
+                    b->shape = s;
+                    b->grid = b->cus * step_occupancy(s, b->cfg.ng_max, PIC_FP32);
+                    return rebuild_schedule(b) == PIC_OK ? hipSuccess : hipErrorInvalidValue;
+                },
+                [b](const LaunchShape &s) {
+                    return launch_particles(b->table, b->items_dev, b->queue_dev, b->grid, s, b->cfg.ng_max,
+                                            PIC_FP32, 0, b->stream);
+                },
+                &shape);
             off = 0;
             for (pic_run *r : live) {
                 pic_status rs = save_particles(r, tmp + off, true);
@@ -1641,7 +1673,7 @@ pic_status batch_advance(pic_batch *b, int64_t nsteps, std::vector<StepEvents> *
                 ev = &evs->back();
             }
             hipError_t le = launch_step(b->table, b->items_dev, b->queue_dev, b->grid, b->shape,
-                                        b->cfg.ng_max, PIC_FP32, 0, b->cfg.max_runs, b->stream, ev);
+                                        b->cfg.ng_max, PIC_FP32, 0, b->slots_dev, b->nsolve, b->stream, ev);
             if (le != hipSuccess) {
                 b->error = true;
                 return fail(PIC_EDEVICE, "batch step launch failed: %s", hipGetErrorString(le));
@@ -1784,6 +1816,8 @@ extern "C" pic_status pic_batch_destroy(pic_batch *b) {
     if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->items_host) (void)hipHostFree(b->items_host);
     if (b->queue_host) (void)hipHostFree(b->queue_host);
+    if (b->slots_host) (void)hipHostFree(b->slots_host);
+    if (b->slots_dev) (void)hipFree(b->slots_dev);
     if (b->items_dev) (void)hipFree(b->items_dev);
     if (b->queue_dev) (void)hipFree(b->queue_dev);
     if (b->table) (void)hipFree(b->table);

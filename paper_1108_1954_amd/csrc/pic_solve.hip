@@ -526,14 +526,17 @@ __device__ __forceinline__ void solve_run(RunDev *R, const SolveView &V, double 
     }
 }
 
-// Second launch of a step: workgroup b solves run runs[b] for E^{n+1} and
-// records the diagnostics; runs that are idle or finished return at once.
-__global__ __launch_bounds__(kMaxSolveThreads) void solve_kernel(RunDev *runs, int prologue) {
+// Second launch of a step: workgroup b solves run runs[slots[b]] (slots
+// null: runs[b]) for E^{n+1} and records the diagnostics; a slot of -1 and
+// runs that are idle or finished return at once.
+__global__ __launch_bounds__(kMaxSolveThreads) void solve_kernel(RunDev *runs, const int32_t *slots, int prologue) {
     __shared__ double D[kSolveLds];
     __shared__ double red[2 * kRedSlots];
     __shared__ long long redi[kRedSlots];
     __shared__ double red3[2 * kRedSlots];
-    RunDev *R = runs + blockIdx.x;
+    const int slot = slots ? slots[blockIdx.x] : (int)blockIdx.x;
+    if (slot < 0) return;
+    RunDev *R = runs + slot;
     const SolveView V = solve_view(R);
     if (!prologue && V.step >= V.step_target) return;
     solve_run(R, V, D, red, redi, red3, prologue != 0);
@@ -541,9 +544,10 @@ __global__ __launch_bounds__(kMaxSolveThreads) void solve_kernel(RunDev *runs, i
 
 }  // namespace
 
-hipError_t launch_solve(RunDev *runs, int nsolve, int prologue, int ng_max, hipStream_t stream) {
+hipError_t launch_solve(RunDev *runs, const int32_t *slots, int nsolve, int prologue, int ng_max,
+                        hipStream_t stream) {
     if (nsolve <= 0 || ng_max < 2 || ng_max > kMaxNg) return hipErrorInvalidValue;
-    void *args[] = {(void *)&runs, (void *)&prologue};
+    void *args[] = {(void *)&runs, (void *)&slots, (void *)&prologue};
     return hipLaunchKernel((const void *)solve_kernel, dim3(nsolve), dim3(solve_threads(ng_max)), args, 0, stream);
 }
 

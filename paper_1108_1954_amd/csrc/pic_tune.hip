@@ -2,7 +2,9 @@
 //
 // The particle pass is timed with HIP events for every candidate shape
 // (threads per workgroup x particle vectors per lane per iteration) on the
-// caller's real state; the caller saves the particle arrays before and
+// caller's real state, five launches each, interleaved across candidates,
+// and scored by the median; the incumbent shape stays unless another is at
+// least 2% faster; the caller saves the particle arrays before and
 // restores them after, so tuning leaves no trace in the results (which do
 // not depend on the shape in any case: tiles and summation orders are fixed
 // by the run alone).  Winners are cached per key (device, precision, grid
@@ -10,6 +12,7 @@
 // names a file, across processes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -17,6 +20,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <vector>
 
 #include "pic_internal.h"
 
@@ -87,50 +91,67 @@ bool tune_lookup(const std::string &key, LaunchShape *out) {
 }
 
 hipError_t tune_shapes(const std::string &key, int precision, hipStream_t stream,
+                       const std::function<hipError_t(const LaunchShape &)> &prepare,
                        const std::function<hipError_t(const LaunchShape &)> &launch, LaunchShape *best) {
     // intermediate sizes: 640 threads fit two workgroups per CU at five
     // waves per SIMD, 768 one of twelve waves; each wins on some workloads
     static const int kBlocks[] = {256, 512, 640, 768, 1024};
     static const int kUnrolls[] = {1, 2, 4};
-    constexpr int kReps = 3;
-    hipEvent_t e0, e1;
-    hipError_t err = hipEventCreate(&e0);
-    if (err != hipSuccess) return err;
-    if ((err = hipEventCreate(&e1)) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return err;
-    }
-    double best_ms = 1e30;
-    LaunchShape winner = *best;
-    for (int blk : kBlocks) {
+    constexpr int kCand = 15;
+    constexpr int kRounds = 5;
+    // A challenger must beat the incumbent (the shape passed in) by this
+    // fraction of its time: shapes within noise of each other do not flip
+    // from one process to the next.
+    constexpr double kMargin = 0.02;
+    LaunchShape cand[kCand];
+    int nc = 0;
+    for (int blk : kBlocks)
         for (int un : kUnrolls) {
-            LaunchShape s;
-            s.block = blk;
-            s.unroll = un;
-            if ((err = step_prepare(s, precision)) != hipSuccess) break;
-            if ((err = launch(s)) != hipSuccess) break;           // warm-up
-            if ((err = hipEventRecord(e0, stream)) != hipSuccess) break;
-            for (int r = 0; r < kReps && err == hipSuccess; ++r) err = launch(s);
-            if (err != hipSuccess) break;
-            if ((err = hipEventRecord(e1, stream)) != hipSuccess) break;
-            if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
-            float ms = 0;
-            if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-            if (ms / kReps < best_ms) {
-                best_ms = ms / kReps;
-                winner = s;
+            cand[nc].block = blk;
+            cand[nc].unroll = un;
+            ++nc;
+        }
+    hipEvent_t ev[2 * kCand] = {};
+    hipError_t err = hipSuccess;
+    for (int i = 0; i < 2 * kCand && err == hipSuccess; ++i) err = hipEventCreate(&ev[i]);
+    std::vector<float> t((size_t)kCand * kRounds, 0.0f);
+    // round 0 warms every candidate up; rounds 1..kRounds are timed, each
+    // launch on its own and the candidates interleaved, so that drift of the
+    // device's clocks affects them alike; prepare() runs outside the timing
+    for (int round = 0; round <= kRounds && err == hipSuccess; ++round) {
+        for (int c = 0; c < kCand && err == hipSuccess; ++c) {
+            if ((err = step_prepare(cand[c], precision)) != hipSuccess) break;
+            if ((err = prepare(cand[c])) != hipSuccess) break;
+            if (round > 0 && (err = hipEventRecord(ev[2 * c], stream)) != hipSuccess) break;
+            if ((err = launch(cand[c])) != hipSuccess) break;
+            if (round > 0 && (err = hipEventRecord(ev[2 * c + 1], stream)) != hipSuccess) break;
+            if (round > 0) {
+                if ((err = hipEventSynchronize(ev[2 * c + 1])) != hipSuccess) break;
+                float ms = 0;
+                if ((err = hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1])) != hipSuccess) break;
+                t[(size_t)c * kRounds + (round - 1)] = ms;
             }
         }
-        if (err != hipSuccess) break;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
     if (err != hipSuccess) return err;
-    *best = winner;
+    double med[kCand];
+    int incumbent = -1, fastest = 0;
+    for (int c = 0; c < kCand; ++c) {
+        std::vector<float> v(t.begin() + (long)c * kRounds, t.begin() + (long)(c + 1) * kRounds);
+        std::sort(v.begin(), v.end());
+        med[c] = v[kRounds / 2];
+        if (cand[c].block == best->block && cand[c].unroll == best->unroll) incumbent = c;
+        if (med[c] < med[fastest]) fastest = c;
+    }
+    int pick = fastest;
+    if (incumbent >= 0 && !(med[fastest] < (1.0 - kMargin) * med[incumbent])) pick = incumbent;
+    *best = cand[pick];
     std::lock_guard<std::mutex> g(g_mu);
     load_file_locked();
-    g_cache[key] = winner;
-    append_file_locked(key, winner, best_ms);
+    g_cache[key] = cand[pick];
+    append_file_locked(key, cand[pick], med[pick]);
     return hipSuccess;
 }
 
