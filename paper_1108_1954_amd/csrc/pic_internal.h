@@ -62,14 +62,14 @@ struct WorkItem {
     int32_t pad_;
 };
 
-// Work queue of a batched particle pass (device memory): workgroups take
-// items in list order through `next`; the last workgroup to find the queue
-// empty (counted in `done`) resets both to 0 for the next launch.
+// Work queue of a batched particle pass (device memory): workgroup b takes
+// item b first, then items grid, grid + 1, ... in list order through the
+// ticket counter `next`; the workgroup that draws the launch's last ticket
+// resets it to 0 for the next launch.
 struct WorkQueue {
     uint32_t next;
-    uint32_t done;
     uint32_t nitems;
-    uint32_t pad_;
+    uint32_t pad_[2];
 };
 
 // Particles per block unit: tile t of a run owns units t, t + ntiles, ...

@@ -388,10 +388,10 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
 
 // Particle pass.  Single run (items == nullptr): workgroup b takes an
 // even share of the run's tiles.  Batch: workgroups take work items (chunks
-// of some run's tiles, largest first) from the shared queue until it is
-// empty; the last workgroup to find it empty resets the queue for the next
-// launch.  Any workgroup may take any chunk: nothing a chunk computes
-// depends on who computes it (per-tile partials, integer grid sums).
+// of some run's tiles, largest first): workgroup b item b, then the next
+// ones from the shared queue until it is empty (see WorkQueue).  Any
+// workgroup may take any chunk: nothing a chunk computes depends on who
+// computes it (per-tile partials, integer grid sums).
 template <typename T, int BLOCK, int UNROLL, bool PUSH>
 __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkItem *items, WorkQueue *queue,
                                                     int ng_lds) {
@@ -402,11 +402,24 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
     T *Et = reinterpret_cast<T *>(lds + ng_lds + 2);
     for (int g = threadIdx.x; g < ng_lds + 2; g += BLOCK) Sl[g] = 0ull;
     const uint32_t nitems = items ? queue->nitems : 1u;
+    const uint32_t grid = gridDim.x;
     int prev_run = -1;
     for (uint32_t round = 0;; ++round) {
         uint32_t it = round;                          // single run: one chunk per workgroup
-        if (items) {
-            if (threadIdx.x == 0) s_item = atomicAdd(&queue->next, 1u);
+        if (items && round == 0) {
+            it = blockIdx.x;                          // first item: no queue traffic
+        } else if (items) {
+            if (threadIdx.x == 0) {
+                // Tickets 0, 1, ... map to items grid, grid + 1, ...; every
+                // workgroup that had a first item draws exactly one ticket
+                // past the list and stops, so the holder of the last ticket
+                // knows that no other workgroup touches `next` again.
+                const uint32_t t = atomicAdd(&queue->next, 1u);
+                const uint32_t fetching = nitems < grid ? nitems : grid;
+                const uint32_t more = nitems > grid ? nitems - grid : 0u;
+                if (t == more + fetching - 1u) atomicExch(&queue->next, 0u);
+                s_item = grid + t;
+            }
             __syncthreads();
             it = s_item;
             __syncthreads();                          // s_item is rewritten next round
@@ -431,13 +444,6 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
             process_chunk<T, BLOCK, UNROLL, PUSH>(R, tb, te, chunk, r != prev_run, Sl, Et, &s_tile);
             prev_run = r;
         }
-    }
-    if (!items) return;
-    // Every other workgroup's last take from the queue has returned before
-    // its `done` increment, so the last one can reset both counters.
-    if (threadIdx.x == 0 && atomicAdd(&queue->done, 1u) == gridDim.x - 1) {
-        atomicExch(&queue->next, 0u);
-        atomicExch(&queue->done, 0u);
     }
 }
 

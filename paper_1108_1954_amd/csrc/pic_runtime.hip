@@ -1127,7 +1127,9 @@ struct pic_batch {
     int64_t next_id = 1;
     int64_t launches = 0;             // batch step launches issued
     bool dirty = true;                // work list needs a rebuild
-    hipGraphExec_t graph = nullptr;
+    // Captured step graphs, one per solve-launch size (nsolve): switching
+    // between sizes as runs come and go replays a graph captured before.
+    std::map<int, hipGraphExec_t> graphs;
     // Completion marks: events recorded on the batch stream after launches
     // and admissions, in order; `seq` numbers them.
     struct Mark {
@@ -1199,11 +1201,7 @@ pic_status rebuild_schedule(pic_batch *b) {
     int bucket = 1;
     while (bucket < nact) bucket <<= 1;
     for (int k = nact; k < bucket; ++k) b->slots_host[k] = -1;
-    if (bucket != b->nsolve && b->graph) {             // the captured solve launches have the old grid
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-    }
-    b->nsolve = bucket;
+    b->nsolve = bucket;                                // selects the graph with that solve grid
     HIP_TRY(hipMemcpyAsync(b->slots_dev, b->slots_host, sizeof(int32_t) * (size_t)bucket, hipMemcpyHostToDevice,
                            b->stream));
     const int n = (int)chunks.size();
@@ -1211,8 +1209,8 @@ pic_status rebuild_schedule(pic_batch *b) {
         const Chunk &c = chunks[(size_t)k];
         b->items_host[k] = {c.slot, c.tb, c.te, c.index, c.count, 0};
     }
-    // The previous launch left next = done = 0; this copy is ordered after it.
-    *b->queue_host = WorkQueue{0u, 0u, (uint32_t)n, 0u};
+    // The previous launch left next = 0; this copy is ordered after it.
+    *b->queue_host = WorkQueue{0u, (uint32_t)n, {0u, 0u}};
     HIP_TRY(hipMemcpyAsync(b->queue_dev, b->queue_host, sizeof(WorkQueue), hipMemcpyHostToDevice, b->stream));
     if (n) HIP_TRY(hipMemcpyAsync(b->items_dev, b->items_host, sizeof(WorkItem) * (size_t)n,
                                   hipMemcpyHostToDevice, b->stream));
@@ -1266,15 +1264,20 @@ pic_status enqueue_member_sorts(pic_batch *b) {
     return PIC_OK;
 }
 
+// One batch step (particle pass, then the solve launch over the active
+// slots) on `stream`.
+hipError_t batch_launch(const pic_batch *b, hipStream_t stream, const StepEvents *ev = nullptr) {
+    return launch_step(b->table, b->items_dev, b->queue_dev, b->grid, b->shape, b->cfg.ng_max, PIC_FP32, 0,
+                       b->slots_dev, b->nsolve, stream, ev);
+}
+
 pic_status ensure_graph(pic_batch *b) {
-    if (b->graph || b->cfg.graph_steps <= 1) return PIC_OK;
+    if (b->cfg.graph_steps <= 1 || b->graphs.count(b->nsolve)) return PIC_OK;
     const pic_batch *bc = b;
-    return capture_graph(
-        [bc](hipStream_t s) {
-            return launch_step(bc->table, bc->items_dev, bc->queue_dev, bc->grid, bc->shape,
-                               bc->cfg.ng_max, PIC_FP32, 0, bc->slots_dev, bc->nsolve, s);
-        },
-        b->cfg.graph_steps, &b->graph);
+    hipGraphExec_t exec = nullptr;
+    pic_status st = capture_graph([bc](hipStream_t s) { return batch_launch(bc, s); }, b->cfg.graph_steps, &exec);
+    if (st == PIC_OK) b->graphs[b->nsolve] = exec;
+    return st;
 }
 
 pic_status add_mark(pic_batch *b) {
@@ -1624,9 +1627,9 @@ pic_status batch_choose_shape(pic_batch *b) {
     // Tuning launches change the work list; the graph only has to go when
     // the launch itself (shape or grid) changed.
     b->dirty = true;
-    if (b->graph && (b->grid != old_grid || old_shape.block != shape.block || old_shape.unroll != shape.unroll)) {
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
+    if (b->grid != old_grid || old_shape.block != shape.block || old_shape.unroll != shape.unroll) {
+        for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
+        b->graphs.clear();
     }
     return PIC_OK;
 }
@@ -1656,7 +1659,7 @@ pic_status batch_advance(pic_batch *b, int64_t nsteps, std::vector<StepEvents> *
         }
         if (!evs && G > 1 && k >= G) {
             while (k >= G) {
-                HIP_TRY(hipGraphLaunch(b->graph, b->stream));
+                HIP_TRY(hipGraphLaunch(b->graphs.at(b->nsolve), b->stream));
                 b->launches += G;
                 left -= G;
                 k -= G;
@@ -1672,8 +1675,7 @@ pic_status batch_advance(pic_batch *b, int64_t nsteps, std::vector<StepEvents> *
                 evs->push_back(e);
                 ev = &evs->back();
             }
-            hipError_t le = launch_step(b->table, b->items_dev, b->queue_dev, b->grid, b->shape,
-                                        b->cfg.ng_max, PIC_FP32, 0, b->slots_dev, b->nsolve, b->stream, ev);
+            hipError_t le = batch_launch(b, b->stream, ev);
             if (le != hipSuccess) {
                 b->error = true;
                 return fail(PIC_EDEVICE, "batch step launch failed: %s", hipGetErrorString(le));
@@ -1812,7 +1814,7 @@ extern "C" pic_status pic_batch_destroy(pic_batch *b) {
     }
     if (b->idle_host) (void)hipHostFree(b->idle_host);
     if (b->io_stream) (void)hipStreamDestroy(b->io_stream);
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
     if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->items_host) (void)hipHostFree(b->items_host);
     if (b->queue_host) (void)hipHostFree(b->queue_host);

@@ -16,6 +16,7 @@ namespace pic1d {
 namespace {
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxSolveThreads = 1024;  // largest solve workgroup
 
@@ -461,47 +462,99 @@ __device__ __forceinline__ void solve_run(RunDev *R, const SolveView &V, double 
     // holds every S_g): exact sum_g S_g and the two diagnostics sums
     solve_sum3(tot, a1, a2, redi, red3, nthr);
     const double meanS = (double)tot / (double)ng;
-    double C = 0.0;
-    if (cg) {
-        __syncthreads();                          // D holds every S_g
-        cg_paper(V, D, red, par, meanS, nthr);               // D: E_g
-    } else {
-        const double scale = V.qfac * V.dx;       // face-field change per unit of S
-        const int seg = (ng + nthr - 1) / nthr;
-        const int g0 = worker ? min(tid * seg, ng) : ng, g1 = min(g0 + seg, ng);
-        double acc = 0.0;
-        for (int g = g0; g < g1; ++g) {
-            acc += (D[dpad(g)] - meanS) * scale;
-            D[dpad(g)] = acc;
-        }
-        const double off = solve_exclusive_scan(acc, red, par, nthr);
-        double csum = 0.0;
-        for (int g = g0; g < g1; ++g) {
-            double fv = D[dpad(g)] + off;
-            D[dpad(g)] = fv;
-            csum += fv;
-        }
-        C = -solve_sum(csum, red, par, nthr) / (double)ng;   // syncs: D complete
-    }
     const double ecoef = V.ecoef;
     float *Ehat = V.Ehat;
     double *Ehat64 = V.Ehat64;
     double *E64 = V.E64;
     double we = 0.0;
-    if (worker) {
-        for (int g = tid; g < ng; g += nthr) {
-            double E;
-            if (cg) {
-                E = D[g];
-            } else {
-                double left = D[dpad(g == 0 ? ng - 1 : g - 1)];
-                E = 0.5 * (left + D[dpad(g)]) + C;
+    if (cg) {
+        __syncthreads();                          // D holds every S_g
+        cg_paper(V, D, red, par, meanS, nthr);               // D: E_g
+        if (worker) {
+            for (int g = tid; g < ng; g += nthr) {
+                const double E = D[g];
+                E64[g] = E;
+                const double eh = E * ecoef;
+                Ehat[g] = (float)eh;
+                if (Ehat64) Ehat64[g] = eh;
+                we += E * E;
             }
-            E64[g] = E;
-            double eh = E * ecoef;
-            Ehat[g] = (float)eh;
-            if (Ehat64) Ehat64[g] = eh;
-            we += E * E;
+        }
+    } else {
+        // Each thread owns the contiguous nodes [g0, g1) (at most kSolvePer):
+        // their S_g are read from LDS at once, the face values are formed in
+        // registers, and only the segment's last one goes back to LDS (slot
+        // g1 - 1), where the next thread's first node finds its left face.
+        const double scale = V.qfac * V.dx;       // face-field change per unit of S
+        const int seg = (ng + nthr - 1) / nthr;
+        const int g0 = worker ? min(tid * seg, ng) : ng, g1 = min(g0 + seg, ng);
+        const int n = g1 - g0;
+        double f[kSolvePer];
+#pragma unroll
+        for (int j = 0; j < kSolvePer; ++j) f[j] = j < n ? D[dpad(g0 + j)] : 0.0;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < kSolvePer; ++j) {
+            if (j < n) {
+                acc += (f[j] - meanS) * scale;
+                f[j] = acc;
+            }
+        }
+        const double off = solve_exclusive_scan(acc, red, par, nthr);
+        double csum = 0.0;
+#pragma unroll
+        for (int j = 0; j < kSolvePer; ++j) {
+            if (j < n) {
+                f[j] += off;
+                csum += f[j];
+            }
+        }
+        // every thread read its segment before the scan's barrier
+        if (n > 0) D[dpad(g1 - 1)] = f[n - 1];
+        const double C = -solve_sum(csum, red, par, nthr) / (double)ng;   // syncs: last faces in D
+        if (n > 0) {
+            double left = D[dpad(g0 == 0 ? ng - 1 : g0 - 1)];
+            double e[kSolvePer];
+#pragma unroll
+            for (int j = 0; j < kSolvePer; ++j) {
+                e[j] = 0.5 * (left + f[j]) + C;
+                left = f[j];
+            }
+            if (n == kSolvePer) {
+                // a full segment: 16-byte stores (g0 is a multiple of 8)
+#pragma unroll
+                for (int j = 0; j < kSolvePer; j += 2) {
+                    f64x2 ev, hv;
+                    ev.x = e[j];
+                    ev.y = e[j + 1];
+                    hv.x = e[j] * ecoef;
+                    hv.y = e[j + 1] * ecoef;
+                    *reinterpret_cast<f64x2 *>(E64 + g0 + j) = ev;
+                    if (Ehat64) *reinterpret_cast<f64x2 *>(Ehat64 + g0 + j) = hv;
+                }
+#pragma unroll
+                for (int j = 0; j < kSolvePer; j += 4) {
+                    f32x4 tv;
+                    tv.x = (float)(e[j] * ecoef);
+                    tv.y = (float)(e[j + 1] * ecoef);
+                    tv.z = (float)(e[j + 2] * ecoef);
+                    tv.w = (float)(e[j + 3] * ecoef);
+                    *reinterpret_cast<f32x4 *>(Ehat + g0 + j) = tv;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < kSolvePer; ++j) {
+                    if (j < n) {
+                        E64[g0 + j] = e[j];
+                        const double eh = e[j] * ecoef;
+                        Ehat[g0 + j] = (float)eh;
+                        if (Ehat64) Ehat64[g0 + j] = eh;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kSolvePer; ++j)
+                if (j < n) we += e[j] * e[j];
         }
     }
     we = 0.5 * V.dx * solve_sum(we, red, par, nthr);

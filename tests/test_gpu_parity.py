@@ -5,6 +5,7 @@ work (the fixed-point charge deposit) must match bit for bit; floating-point
 results are held to tolerances derived from the arithmetic (see
 `push_tolerance`).  Every call goes through the C ABI.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -283,6 +284,8 @@ def small_ensemble(n, seed=3):
 
 
 def test_batched_runs_equal_the_same_runs_alone():
+    """Six runs of different (np, ng <= 2048) in one batch: state, grids and
+    history equal each run stepped alone, bit for bit."""
     specs = small_ensemble(6)
     parts = [s.particles() for s in specs]
     alone = []
@@ -311,6 +314,38 @@ def test_batched_runs_equal_the_same_runs_alone():
             assert d["step"] == s.nsteps
         done = P.pic_batch_poll(b)
         assert sorted(done) == sorted(ids)
+    finally:
+        P.pic_batch_destroy(b)
+
+
+def test_batch_mixing_solvers_and_step_counts_equals_runs_alone():
+    """A batch of a run with the paper's CG solver (5 steps) and runs with the
+    exact solver (14 to 20 steps): the solve launch shrinks as runs finish
+    (a different captured graph), and every run, both solvers, equals the
+    same run alone, bit for bit."""
+    specs = small_ensemble(4, seed=12)
+    specs = [dataclasses.replace(s, nsteps=5 if k == 0 else 11 + 3 * k) for k, s in enumerate(specs)]
+    parts = [s.particles() for s in specs]
+    solvers = [P.PIC_SOLVE_CG_PAPER] + [P.PIC_SOLVE_EXACT] * (len(specs) - 1)
+    params = [P.make_params(s.L, s.ng, s.np_, s.dt, history_cap=s.nsteps, solver=sv)
+              for s, sv in zip(specs, solvers)]
+    alone = []
+    for s, p, (x, v) in zip(specs, params, parts):
+        with P.Run(p, x, v) as r:
+            r.step(s.nsteps)
+            alone.append((r.raw(), r.grid()[1], r.history()))
+    b = P.pic_batch_create(1 << 30, 2048, max_runs=8, graph_steps=4, stream=P.current_stream())
+    try:
+        ids = [P.pic_batch_admit(b, p, x, v, s.nsteps) for s, p, (x, v) in zip(specs, params, parts)]
+        P.pic_batch_step(b, 3)
+        P.pic_batch_step(b, 100)                       # runs stop at their own step counts
+        for rid, s, (raw, E, hist) in zip(ids, specs, alone):
+            view = P.pic_batch_run(b, rid)
+            u, w = P.pic_read_raw(view, s.np_)
+            np.testing.assert_array_equal(u, raw[0])
+            np.testing.assert_array_equal(w, raw[1])
+            np.testing.assert_array_equal(P.pic_read_grid(view, s.ng)[1], E)
+            np.testing.assert_array_equal(P.pic_read_history(view, 0, s.nsteps), hist)
     finally:
         P.pic_batch_destroy(b)
 
