@@ -231,6 +231,16 @@ def workload_probe(args, P, torch, nbytes=2 << 30):
     b = torch.ones(n, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     ms = P.pic_bandwidth_probe(a.data_ptr(), b.data_ptr(), n, reps=args.steps, stream=P.current_stream())
+    # The same swap over exactly the state of each workload's particle pass
+    # (one launch per swap, as one pass is one launch): the achievable rate
+    # for that many bytes, launch ramp and tail included.
+    sized = {}
+    for name, npart in (("serving batch of 8 runs", 1_804_773), ("paper workload", 8_192_000),
+                        ("single run 2^26", 1 << 26), ("ensemble", 145_439_881)):
+        m = npart // 4 * 4
+        t = P.pic_bandwidth_probe(a.data_ptr(), b.data_ptr(), m, reps=max(args.steps, 50),
+                                  stream=P.current_stream())
+        sized[name] = {"particles": m, "bytes": 16 * m, "swap_us": 1e3 * t, "GBps": 16 * m / (t * 1e6)}
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -245,7 +255,7 @@ def workload_probe(args, P, torch, nbytes=2 << 30):
     return {"workload": "bandwidth reference", "swap_bytes": 16 * n, "swap_ms": ms,
             "swap_GBps": 16 * n / (ms * 1e6), "swap_frac_of_peak": 16 * n / (ms * 1e6) / PEAK_HBM_GBPS,
             "torch_copy_bytes": 2 * COPY_BYTES, "torch_copy_ms": mc,
-            "torch_copy_GBps": 2 * COPY_BYTES / (mc * 1e6)}
+            "torch_copy_GBps": 2 * COPY_BYTES / (mc * 1e6), "swap_at_workload_sizes": sized}
 
 
 def main():

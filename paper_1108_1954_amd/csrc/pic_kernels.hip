@@ -257,10 +257,12 @@ __device__ __forceinline__ void run_one(T *U, T *W, int64_t q, const T *Et, unsi
 // chunk together whatever the tile count.  Each lane handles UNROLL vectors
 // of VEC particles per iteration, all loads issued before any compute; a
 // lane's particles are accumulated in index order for every UNROLL, so the
-// tile partial sums depend only on the run.
+// tile partial sums depend only on the run.  The deposits stay in the
+// private grid Sl (merged by the caller); the gather table is loaded into Et
+// only when `load_table` (the previous chunk was of another run).
 template <typename T, int BLOCK, int UNROLL, bool PUSH>
-__device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_table,
-                              unsigned long long *Sl, T *Et, int *next_tile) {
+__device__ void process_chunk(RunDev *R, int tb, int te, bool load_table, unsigned long long *Sl, T *Et,
+                              int *next_tile) {
     using V = typename Vec<T>::type;
     constexpr int VEC = Vec<T>::n;
     constexpr int PER = 64 * VEC * UNROLL;
@@ -277,7 +279,6 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
     T *U = (T *)R->u;
     T *W = (T *)R->w;
     double *part = R->tile_part;
-    unsigned long long *S = R->S;                    // read now: later the pass's stores could alias it
     const T ngf = (T)ng;
     const T hi = ngf + T(0.5);
     if (PUSH && load_table) fill_table<T, BLOCK>(gather_table<T>(R), Et, ng);
@@ -363,11 +364,16 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
     }
     if (flags) atomicOr(&R->flags, flags);
     __syncthreads();
-    // Merge the private grid into the run's grid with 64-bit atomics, folding
-    // the two ghost nodes.  No fence: the solve runs in the next launch, after
-    // the kernel boundary has made every merge visible.  Starting at a
-    // chunk-dependent rotation spreads concurrent merges over addresses.
-    const int rot = (int)(((unsigned)chunk * 97u) % (unsigned)ng);
+}
+
+// Merge the private grid into the run's grid S[ng] with 64-bit atomics,
+// folding the two ghost nodes, and clear it.  No fence: the solve runs in
+// the next launch, after the kernel boundary has made every merge visible.
+// Starting at a workgroup-dependent rotation spreads concurrent merges over
+// addresses.
+template <int BLOCK>
+__device__ void merge_grid(unsigned long long *S, int ng, int rot_seed, unsigned long long *Sl) {
+    const int rot = (int)(((unsigned)rot_seed * 97u) % (unsigned)ng);
     for (int k = threadIdx.x; k < ng; k += BLOCK) {
         int c = k + rot;
         if (c >= ng) c -= ng;
@@ -391,7 +397,9 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int chunk, bool load_ta
 // of some run's tiles, largest first): workgroup b item b, then the next
 // ones from the shared queue until it is empty (see WorkQueue).  Any
 // workgroup may take any chunk: nothing a chunk computes depends on who
-// computes it (per-tile partials, integer grid sums).
+// computes it (per-tile partials, integer grid sums).  A workgroup merges
+// its private grid when it moves to another run and when it is done, so
+// chunks of one run in a row cost one table load and one merge.
 template <typename T, int BLOCK, int UNROLL, bool PUSH>
 __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkItem *items, WorkQueue *queue,
                                                     int ng_lds) {
@@ -404,6 +412,8 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
     const uint32_t nitems = items ? queue->nitems : 1u;
     const uint32_t grid = gridDim.x;
     int prev_run = -1;
+    unsigned long long *S_pend = nullptr;             // grid of prev_run, merged when the run changes
+    int ng_pend = 0, rot_pend = 0;
     for (uint32_t round = 0;; ++round) {
         uint32_t it = round;                          // single run: one chunk per workgroup
         if (items && round == 0) {
@@ -441,10 +451,19 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
         RunDev *R = runs + r;
         // the prologue (initial deposit) runs whatever the step target, even 0
         if (te > tb && !(PUSH && R->step >= R->step_target) && R->ng <= ng_lds) {
-            process_chunk<T, BLOCK, UNROLL, PUSH>(R, tb, te, chunk, r != prev_run, Sl, Et, &s_tile);
+            if (r != prev_run) {
+                // A new run: the previous run's grid goes out first (chunks of
+                // one run in a row share the private grid and the table).
+                if (prev_run >= 0) merge_grid<BLOCK>(S_pend, ng_pend, rot_pend, Sl);
+                S_pend = R->S;
+                ng_pend = R->ng;
+                rot_pend = chunk;
+            }
+            process_chunk<T, BLOCK, UNROLL, PUSH>(R, tb, te, r != prev_run, Sl, Et, &s_tile);
             prev_run = r;
         }
     }
+    if (prev_run >= 0) merge_grid<BLOCK>(S_pend, ng_pend, rot_pend, Sl);
 }
 
 
