@@ -20,8 +20,11 @@ constexpr int kWave = 64;
 struct RunDev {
     void *u, *w;                 // state: s = x/dx + 1/2 in [1/2, ng + 1/2), w = v dt/dx
     void *u_alt, *w_alt;         // cell-sort destination (ping-pong), may be null
-    unsigned long long *S;       // [ng] fixed-point charge sums, zero between steps
-    unsigned long long *S_last;  // [ng] copy of S from the latest solve
+    // [ng] fixed-point charge sums, two buffers: deposit d (d = 0 at
+    // creation, n + 1 in step n) goes to S01[d & 1]; the pass of step n clears
+    // S01[n & 1] (deposit n, consumed by the previous solve), so after N steps
+    // S01[N & 1] holds the latest deposit and S01[(N + 1) & 1] is zero.
+    unsigned long long *S01[2];
     float *Ehat;                 // [ng] gather table  E qm dt^2 / dx   (FP32)
     double *Ehat64;              // [ng] same table in FP64 (FP64 state), may be null
     double *E64;                 // [ng] node field (FP64)

@@ -435,32 +435,45 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
             __syncthreads();                          // s_item is rewritten next round
         }
         if (it >= nitems) break;
-        int r = 0, tb, te, chunk;
+        int r = 0, tb, te, chunk, nchunks;
         if (items) {
             const WorkItem wi = items[it];
             r = wi.run;
             tb = wi.tile_begin;
             te = wi.tile_end;
             chunk = wi.chunk;
+            nchunks = wi.nchunks;
         } else {
             const int64_t nt = runs[0].ntiles;
             tb = (int)(nt * blockIdx.x / gridDim.x);
             te = (int)(nt * (blockIdx.x + 1) / gridDim.x);
             chunk = blockIdx.x;
+            nchunks = gridDim.x;
         }
         RunDev *R = runs + r;
         // the prologue (initial deposit) runs whatever the step target, even 0
-        if (te > tb && !(PUSH && R->step >= R->step_target) && R->ng <= ng_lds) {
-            if (r != prev_run) {
-                // A new run: the previous run's grid goes out first (chunks of
-                // one run in a row share the private grid and the table).
-                if (prev_run >= 0) merge_grid<BLOCK>(S_pend, ng_pend, rot_pend, Sl);
-                S_pend = R->S;
-                ng_pend = R->ng;
-                rot_pend = chunk;
+        if (!(PUSH && R->step >= R->step_target) && R->ng <= ng_lds) {
+            // deposit d = step + 1 (the prologue's: 0) goes to S01[d & 1]; this
+            // chunk clears its share of the other buffer, deposit d - 1, which
+            // the previous launch's solve has read
+            const int dep = PUSH ? (int)((R->step + 1) & 1) : 0;
+            unsigned long long *Sclr = R->S01[dep ^ 1];
+            const int ngr = R->ng;
+            if (te > tb) {
+                if (r != prev_run) {
+                    // A new run: the previous run's grid goes out first (chunks
+                    // of one run in a row share the private grid and the table).
+                    if (prev_run >= 0) merge_grid<BLOCK>(S_pend, ng_pend, rot_pend, Sl);
+                    S_pend = R->S01[dep];
+                    ng_pend = ngr;
+                    rot_pend = chunk;
+                }
+                process_chunk<T, BLOCK, UNROLL, PUSH>(R, tb, te, r != prev_run, Sl, Et, &s_tile);
+                prev_run = r;
             }
-            process_chunk<T, BLOCK, UNROLL, PUSH>(R, tb, te, r != prev_run, Sl, Et, &s_tile);
-            prev_run = r;
+            const int g1 = (int)((int64_t)ngr * (chunk + 1) / nchunks);
+            for (int g = (int)((int64_t)ngr * chunk / nchunks) + (int)threadIdx.x; g < g1; g += BLOCK)
+                Sclr[g] = 0ull;
         }
     }
     if (prev_run >= 0) merge_grid<BLOCK>(S_pend, ng_pend, rot_pend, Sl);

@@ -125,7 +125,7 @@ int default_tile(int64_t np) {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t u, w, u_alt, w_alt, sort, S, S_last, Ehat, Ehat64, E64, part, hist, total;
+    size_t u, w, u_alt, w_alt, sort, S0, S1, Ehat, Ehat64, E64, part, hist, total;
     int tile, ntiles;
     size_t esize;
     bool sorting;         // alternate particle arrays and sort scratch present
@@ -151,8 +151,8 @@ Layout make_layout(const pic_params *p) {
         L.w_alt = take(np_pad * L.esize);
         L.sort = take(sort_scratch_bytes(p->np, p->ng));
     }
-    L.S = take((size_t)p->ng * 8);
-    L.S_last = take((size_t)p->ng * 8);
+    L.S0 = take((size_t)p->ng * 8);
+    L.S1 = take((size_t)p->ng * 8);
     L.Ehat = take((size_t)p->ng * 4);
     L.Ehat64 = take((size_t)p->ng * 8);
     L.E64 = take((size_t)p->ng * 8);
@@ -290,8 +290,8 @@ void carve(pic_run *r) {
     h.w = b + L.w;
     h.u_alt = L.sorting ? b + L.u_alt : nullptr;
     h.w_alt = L.sorting ? b + L.w_alt : nullptr;
-    h.S = (unsigned long long *)(b + L.S);
-    h.S_last = (unsigned long long *)(b + L.S_last);
+    h.S01[0] = (unsigned long long *)(b + L.S0);
+    h.S01[1] = (unsigned long long *)(b + L.S1);
     h.Ehat = (float *)(b + L.Ehat);
     h.Ehat64 = r->p.precision == PIC_FP64 ? (double *)(b + L.Ehat64) : nullptr;
     h.E64 = (double *)(b + L.E64);
@@ -345,8 +345,8 @@ pic_status upload_particles(pic_run *r, const double *x0, const double *v) {
 // `desc` (host memory that stays valid until the copy has run) and run the
 // prologue (deposit of x^0 and solve for E^0).  Nothing waits.
 pic_status queue_device_init(pic_run *r, const RunDev *desc) {
-    HIP_TRY(hipMemsetAsync(r->host.S, 0, (size_t)r->p.ng * 8, r->stream));
-    HIP_TRY(hipMemsetAsync(r->host.S_last, 0, (size_t)r->p.ng * 8, r->stream));
+    HIP_TRY(hipMemsetAsync(r->host.S01[0], 0, (size_t)r->p.ng * 8, r->stream));
+    HIP_TRY(hipMemsetAsync(r->host.S01[1], 0, (size_t)r->p.ng * 8, r->stream));
     HIP_TRY(hipMemsetAsync(r->host.tile_part, 0, (size_t)r->lay.ntiles * kPartCols * 8, r->stream));
     HIP_TRY(hipMemcpyAsync(r->dev, desc, sizeof(RunDev), hipMemcpyHostToDevice, r->stream));
     HIP_TRY(step_prepare(r->shape, r->p.precision));
@@ -363,21 +363,29 @@ pic_status init_device_state(pic_run *r) {
     return PIC_OK;
 }
 
-// Copy a run's particle arrays to/from a scratch buffer (autotuning runs
-// real particle passes on the run's own state and then puts it back; the
-// tile partials those passes write are rewritten by the next real pass).
+// Bytes of a run's state that trial passes change: the particle arrays and
+// both charge-sum buffers.
+size_t state_bytes(const pic_run *r) { return 2 * (size_t)r->p.np * r->lay.esize + 2 * (size_t)r->p.ng * 8; }
+
+// Copy a run's state (state_bytes) to/from a scratch buffer: autotuning runs
+// real particle passes on the run's own state and then puts it back (those
+// passes deposit into one charge-sum buffer and clear the other); the tile
+// partials they write are rewritten by the next real pass.
 pic_status save_particles(const pic_run *r, char *dst, bool restore) {
-    const size_t bytes = (size_t)r->p.np * r->lay.esize;
+    const size_t bytes = (size_t)r->p.np * r->lay.esize, sb = (size_t)r->p.ng * 8;
     char *u = (char *)r->cur_u(), *w = (char *)r->cur_w();
+    char *s0 = (char *)r->host.S01[0], *s1 = (char *)r->host.S01[1];
     if (restore) {
         HIP_TRY(hipMemcpyAsync(u, dst, bytes, hipMemcpyDeviceToDevice, r->stream));
         HIP_TRY(hipMemcpyAsync(w, dst + bytes, bytes, hipMemcpyDeviceToDevice, r->stream));
-        // passes without solves only accumulated into S; clear it and any flag
-        HIP_TRY(hipMemsetAsync(r->host.S, 0, (size_t)r->p.ng * 8, r->stream));
+        HIP_TRY(hipMemcpyAsync(s0, dst + 2 * bytes, sb, hipMemcpyDeviceToDevice, r->stream));
+        HIP_TRY(hipMemcpyAsync(s1, dst + 2 * bytes + sb, sb, hipMemcpyDeviceToDevice, r->stream));
         HIP_TRY(hipMemsetAsync(&r->dev->flags, 0, sizeof(uint32_t), r->stream));
     } else {
         HIP_TRY(hipMemcpyAsync(dst, u, bytes, hipMemcpyDeviceToDevice, r->stream));
         HIP_TRY(hipMemcpyAsync(dst + bytes, w, bytes, hipMemcpyDeviceToDevice, r->stream));
+        HIP_TRY(hipMemcpyAsync(dst + 2 * bytes, s0, sb, hipMemcpyDeviceToDevice, r->stream));
+        HIP_TRY(hipMemcpyAsync(dst + 2 * bytes + sb, s1, sb, hipMemcpyDeviceToDevice, r->stream));
     }
     return PIC_OK;
 }
@@ -401,7 +409,7 @@ pic_status choose_shape(pic_run *r, const DeviceInfo &d) {
         const std::string key = tune_key("run", r->p.precision, r->p.ng, r->p.np);
         if (!tune_lookup(key, &shape)) {
             char *tmp = nullptr;
-            const size_t bytes = 2 * (size_t)r->p.np * r->lay.esize;
+            const size_t bytes = state_bytes(r);
             if (hipMalloc((void **)&tmp, bytes) != hipSuccess)
                 return fail(PIC_ENOMEM, "autotune scratch of %zu bytes", bytes);
             pic_status st = save_particles(r, tmp, false);
@@ -439,7 +447,7 @@ pic_status choose_shape(pic_run *r, const DeviceInfo &d) {
 pic_status choose_sort_period(pic_run *r) {
     constexpr int kReps = 3;
     char *tmp = nullptr;
-    const size_t bytes = 2 * (size_t)r->p.np * r->lay.esize;
+    const size_t bytes = state_bytes(r);
     if (hipMalloc((void **)&tmp, bytes) != hipSuccess)
         return fail(PIC_ENOMEM, "sort-period trial scratch of %zu bytes", bytes);
     hipEvent_t ev[4] = {};
@@ -845,7 +853,7 @@ extern "C" pic_status pic_diagnostics(pic_run *r, pic_diag *diag, double *rho_ou
     diag->pad_ = 0;
     if (rho_out) {
         std::vector<unsigned long long> S((size_t)r->p.ng);
-        HIP_TRY(dev_read(r, S.data(), r->host.S_last, S.size() * 8));
+        HIP_TRY(dev_read(r, S.data(), r->host.S01[d.step & 1], S.size() * 8));
         const double qdx = r->Q / r->dx;
         for (int g = 0; g < r->p.ng; ++g)
             rho_out[g] = r->p.rho0 + qdx * ((double)S[g] / 4294967296.0);
@@ -910,7 +918,11 @@ extern "C" pic_status pic_read_grid(pic_run *r, int64_t *S, double *E, float *Eh
     st = sync_run(r);
     if (st != PIC_OK) return st;
     const size_t ng = (size_t)r->p.ng;
-    if (S) HIP_TRY(dev_read(r, S, r->host.S_last, ng * 8));
+    if (S) {
+        int64_t steps = 0;                            // the latest deposit is in S01[steps & 1]
+        HIP_TRY(dev_read(r, &steps, &r->dev->step, sizeof steps));
+        HIP_TRY(dev_read(r, S, r->host.S01[steps & 1], ng * 8));
+    }
     if (E) HIP_TRY(dev_read(r, E, r->host.E64, ng * 8));
     if (Ehat) HIP_TRY(dev_read(r, Ehat, r->host.Ehat, ng * 4));
     return PIC_OK;
@@ -1581,7 +1593,7 @@ pic_status batch_choose_shape(pic_batch *b) {
     LaunchShape shape = b->shape;
     if (!tune_lookup(key, &shape)) {
         size_t bytes = 0;
-        for (pic_run *r : live) bytes += 2 * (size_t)r->p.np * r->lay.esize;
+        for (pic_run *r : live) bytes += state_bytes(r);
         char *tmp = nullptr;
         if (hipMalloc((void **)&tmp, bytes) != hipSuccess)
             return fail(PIC_ENOMEM, "autotune scratch of %zu bytes", bytes);
@@ -1589,7 +1601,7 @@ pic_status batch_choose_shape(pic_batch *b) {
         size_t off = 0;
         for (pic_run *r : live) {
             if (st == PIC_OK) st = save_particles(r, tmp + off, false);
-            off += 2 * (size_t)r->p.np * r->lay.esize;
+            off += state_bytes(r);
         }
         hipError_t te = hipSuccess;
         if (st == PIC_OK) {
@@ -1611,7 +1623,7 @@ pic_status batch_choose_shape(pic_batch *b) {
             for (pic_run *r : live) {
                 pic_status rs = save_particles(r, tmp + off, true);
                 if (st == PIC_OK) st = rs;
-                off += 2 * (size_t)r->p.np * r->lay.esize;
+                off += state_bytes(r);
             }
         }
         hipError_t se = hipStreamSynchronize(b->stream);

@@ -1,8 +1,8 @@
 // Field solve of the PIC step (gfx950): the second launch of every step.
 //
 // Workgroup b solves run runs[b] (idle and finished runs return at once):
-// it takes the fixed-point charge sums S the particle pass merged, clears
-// them for the next step, solves the periodic three-point Poisson problem
+// it reads the fixed-point charge sums S the particle pass merged (the next
+// step's pass clears them), solves the periodic three-point Poisson problem
 // (Sec. 2.2) exactly, or with the paper's fixed-iteration CG when the run
 // asks for it, forms the central-difference node field, writes E^{n+1} in
 // FP64 and the gather table for the next particle pass, and records the
@@ -139,7 +139,7 @@ __device__ double solve_exclusive_scan(double v, double *red2, int &par, int nth
 // round trip (the store might alias the descriptor, so the compiler cannot
 // keep it in a register); taken by value here they cost one.
 struct SolveView {
-    unsigned long long *S, *S_last;
+    const unsigned long long *S, *S_alt;   // the deposit to read (see solve_kernel), the other buffer
     float *Ehat;
     double *Ehat64, *E64, *hist;
     const double *tile_part;
@@ -150,8 +150,8 @@ struct SolveView {
 
 __device__ __forceinline__ SolveView solve_view(const RunDev *R) {
     SolveView v;
-    v.S = R->S;
-    v.S_last = R->S_last;
+    v.S = R->S01[0];
+    v.S_alt = R->S01[1];
     v.Ehat = R->Ehat;
     v.Ehat64 = R->Ehat64;
     v.E64 = R->E64;
@@ -402,8 +402,7 @@ __device__ __forceinline__ void solve_run(RunDev *R, const SolveView &V, double 
     const int nthr = solve_threads(ng);
     const bool worker = tid < nthr;
     int par = 0;                                   // reduction buffers (see solve_sum)
-    unsigned long long *S = V.S;
-    unsigned long long *S_last = V.S_last;
+    const unsigned long long *S = V.S;
     const bool cg = V.solver == 1;
     const double *part = V.tile_part;
     const int ntiles = V.ntiles;
@@ -431,8 +430,6 @@ __device__ __forceinline__ void solve_run(RunDev *R, const SolveView &V, double 
     for (int k = 0; k < kSolvePer; ++k) {
         const int g = tid + k * nthr;
         if (worker && g < ng) {
-            S[g] = 0ull;
-            S_last[g] = sv[k];
             tot += (long long)sv[k];
             D[cg ? g : dpad(g)] = (double)sv[k];
         }
@@ -590,8 +587,11 @@ __global__ __launch_bounds__(kMaxSolveThreads) void solve_kernel(RunDev *runs, c
     const int slot = slots ? slots[blockIdx.x] : (int)blockIdx.x;
     if (slot < 0) return;
     RunDev *R = runs + slot;
-    const SolveView V = solve_view(R);
+    SolveView V = solve_view(R);
     if (!prologue && V.step >= V.step_target) return;
+    // this launch's deposit d (0 for the prologue, step + 1 otherwise) is in
+    // S01[d & 1] (selected here: a select inside solve_run costs scratch)
+    if (!prologue && ((V.step + 1) & 1)) V.S = V.S_alt;
     solve_run(R, V, D, red, redi, red3, prologue != 0);
 }
 
