@@ -478,7 +478,10 @@ def main():
         "data": "synthetic (seeded SplitMix64 inputs)",
         "config": {"workload": f"batched ensemble: {len(specs)} runs, Np log-uniform [1e4,4e6]"
                                f"{'' if args.np_scale == 1.0 else f' x{args.np_scale}'}, Ng 64..2048, "
-                               "L=0.032 Ng, dt=0.1, one graph-captured persistent launch pair per step",
+                               "L=0.032 Ng, dt=0.1, one graph-captured persistent launch pair per step; "
+                               f"every run admitted for {run_steps} steps (none finishes inside a measured "
+                               f"launch): steps {W + 1}..{W + K} timed after {W} warm-up steps, then "
+                               f"{prof_steps} more with per-launch HIP events",
                    "total_particles": total_np, "runs": len(specs), "ng_max": ng_max,
                    "graph_steps": args.graph_steps, "device": dev.name, "cus": dev.multi_processor_count},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
