@@ -84,12 +84,19 @@ constexpr int kUnit = 1024;
 struct LaunchShape {
     int block = 512;
     int unroll = 2;
+    // Single runs: 0 gives workgroup b the contiguous tiles
+    // [ntiles b / grid, ntiles (b + 1) / grid), 1 the tiles b, b + grid, ...
+    // (the device's wavefronts then work on neighbouring tiles spread over all
+    // CUs, which HBM serves faster when every wavefront has several tiles).
+    // The tiles themselves, and so the results, are the same.  Batches use
+    // their work list.
+    int order = 0;
 };
 
 // Kernel launchers (pic_kernels.hip).  launch_step enqueues one step on
 // `stream` as two launches: the particle pass, then the field solve.
-//   items == nullptr: single run `runs[0]`, tiles split evenly over `grid`
-//   workgroups.  Otherwise the workgroups take items[0 .. queue->nitems)
+//   items == nullptr: single run `runs[0]`, tiles split over `grid`
+//   workgroups in the shape's tile order.  Otherwise the workgroups take items[0 .. queue->nitems)
 //   through the queue.
 //   The solve launch has nsolve workgroups; workgroup b solves
 //   runs[slots[b]] (slots == nullptr: runs[b]); a slot of -1, idle and
@@ -176,11 +183,12 @@ hipError_t launch_swap(void *a, void *b, int64_t nvec, int cus, hipStream_t stre
 
 // Autotuner (pic_tune.hip).  tune_key names a size class; tune_lookup finds
 // a cached shape; tune_shapes times `launch(shape)` (one particle pass on
-// saved state, after an untimed `prepare(shape)`) for every candidate and
-// caches and returns the choice; *best holds the incumbent on entry.
+// saved state, after an untimed `prepare(shape)`) for every candidate (with
+// `orders`, in both tile orders) and caches and returns the choice; *best
+// holds the incumbent on entry.
 std::string tune_key(const char *kind, int precision, int ng, int64_t np);
 bool tune_lookup(const std::string &key, LaunchShape *out);
-hipError_t tune_shapes(const std::string &key, int precision, hipStream_t stream,
+hipError_t tune_shapes(const std::string &key, int precision, bool orders, hipStream_t stream,
                        const std::function<hipError_t(const LaunchShape &)> &prepare,
                        const std::function<hipError_t(const LaunchShape &)> &launch, LaunchShape *best);
 

@@ -261,8 +261,8 @@ __device__ __forceinline__ void run_one(T *U, T *W, int64_t q, const T *Et, unsi
 // private grid Sl (merged by the caller); the gather table is loaded into Et
 // only when `load_table` (the previous chunk was of another run).
 template <typename T, int BLOCK, int UNROLL, bool PUSH>
-__device__ void process_chunk(RunDev *R, int tb, int te, bool load_table, unsigned long long *Sl, T *Et,
-                              int *next_tile) {
+__device__ void process_chunk(RunDev *R, int tb, int te, int tstride, bool load_table, unsigned long long *Sl,
+                              T *Et, int *next_tile) {
     using V = typename Vec<T>::type;
     constexpr int VEC = Vec<T>::n;
     constexpr int PER = 64 * VEC * UNROLL;
@@ -282,16 +282,16 @@ __device__ void process_chunk(RunDev *R, int tb, int te, bool load_table, unsign
     const T ngf = (T)ng;
     const T hi = ngf + T(0.5);
     if (PUSH && load_table) fill_table<T, BLOCK>(gather_table<T>(R), Et, ng);
-    if (threadIdx.x == 0) *next_tile = tb;
+    if (threadIdx.x == 0) *next_tile = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     uint32_t flags = 0;
     const int64_t nfull = np / kUnit;                // full block units of the run
     const bool ragged = nfull * (int64_t)kUnit < np;
     for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(next_tile, 1);
-        t = __builtin_amdgcn_readfirstlane(t);
+        int k = 0;
+        if (lane == 0) k = atomicAdd(next_tile, 1);
+        const int t = tb + __builtin_amdgcn_readfirstlane(k) * tstride;
         if (t >= te) break;
         double a1 = 0.0, a2 = 0.0;
         // Full units of the tile in sub-blocks of PER particles,
@@ -402,7 +402,7 @@ __device__ void merge_grid(unsigned long long *S, int ng, int rot_seed, unsigned
 // chunks of one run in a row cost one table load and one merge.
 template <typename T, int BLOCK, int UNROLL, bool PUSH>
 __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkItem *items, WorkQueue *queue,
-                                                    int ng_lds) {
+                                                    int ng_lds, int order) {
     extern __shared__ unsigned long long lds[];
     __shared__ uint32_t s_item;
     __shared__ int s_tile;
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
             __syncthreads();                          // s_item is rewritten next round
         }
         if (it >= nitems) break;
-        int r = 0, tb, te, chunk, nchunks;
+        int r = 0, tb, te, chunk, nchunks, tstride = 1;
         if (items) {
             const WorkItem wi = items[it];
             r = wi.run;
@@ -445,8 +445,14 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
             nchunks = wi.nchunks;
         } else {
             const int64_t nt = runs[0].ntiles;
-            tb = (int)(nt * blockIdx.x / gridDim.x);
-            te = (int)(nt * (blockIdx.x + 1) / gridDim.x);
+            if (order) {                              // tiles b, b + grid, b + 2 grid, ...
+                tb = blockIdx.x;
+                te = (int)nt;
+                tstride = gridDim.x;
+            } else {                                  // an even share of consecutive tiles
+                tb = (int)(nt * blockIdx.x / gridDim.x);
+                te = (int)(nt * (blockIdx.x + 1) / gridDim.x);
+            }
             chunk = blockIdx.x;
             nchunks = gridDim.x;
         }
@@ -468,7 +474,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
                     ng_pend = ngr;
                     rot_pend = chunk;
                 }
-                process_chunk<T, BLOCK, UNROLL, PUSH>(R, tb, te, r != prev_run, Sl, Et, &s_tile);
+                process_chunk<T, BLOCK, UNROLL, PUSH>(R, tb, te, tstride, r != prev_run, Sl, Et, &s_tile);
                 prev_run = r;
             }
             const int g1 = (int)((int64_t)ngr * (chunk + 1) / nchunks);
@@ -542,7 +548,8 @@ hipError_t launch_particles(RunDev *runs, const WorkItem *items, WorkQueue *queu
     if (grid <= 0 || ng_lds <= 0 || ng_lds > kMaxNg || (items && !queue)) return hipErrorInvalidValue;
     const void *fn = kernel_select(ls, precision, prologue == 0);
     if (!fn) return hipErrorInvalidValue;
-    void *args[] = {(void *)&runs, (void *)&items, (void *)&queue, (void *)&ng_lds};
+    int order = ls.order;
+    void *args[] = {(void *)&runs, (void *)&items, (void *)&queue, (void *)&ng_lds, (void *)&order};
     return hipLaunchKernel(fn, dim3(grid), dim3(ls.block), args, step_lds_bytes(precision, ng_lds),
                            stream);
 }

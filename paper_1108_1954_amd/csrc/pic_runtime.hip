@@ -53,7 +53,7 @@ namespace {
 struct DeviceInfo {
     int cus = 256;
     LaunchShape shape;     // default launch shape
-    bool forced = false;   // shape set through PIC1D_BLOCK / PIC1D_UNROLL
+    bool forced = false;   // shape set through PIC1D_BLOCK / PIC1D_UNROLL / PIC1D_TILE_ORDER
     bool autotune = true;  // PIC1D_AUTOTUNE=0 turns the autotuner off
 };
 
@@ -80,6 +80,10 @@ DeviceInfo device_info() {
             d.shape.unroll = v;
             d.forced = true;
         }
+    }
+    if (const char *o = getenv("PIC1D_TILE_ORDER")) {
+        d.shape.order = atoi(o) != 0 ? 1 : 0;
+        d.forced = true;
     }
     if (const char *a = getenv("PIC1D_AUTOTUNE")) d.autotune = atoi(a) != 0;
     return d;
@@ -417,7 +421,7 @@ pic_status choose_shape(pic_run *r, const DeviceInfo &d) {
             if (st == PIC_OK) {
                 const int cus = d.cus;
                 te = tune_shapes(
-                    key, r->p.precision, r->stream, [](const LaunchShape &) { return hipSuccess; },
+                    key, r->p.precision, true, r->stream, [](const LaunchShape &) { return hipSuccess; },
                     [r, cus](const LaunchShape &s) {
                         return launch_particles(r->dev, nullptr, nullptr, single_run_grid(r, s, cus), s, r->p.ng,
                                                 r->p.precision, 0, r->stream);
@@ -1608,7 +1612,7 @@ pic_status batch_choose_shape(pic_batch *b) {
             // the schedule depends on the shape (grid and chunk sizes): it is
             // rebuilt before each timed launch, outside the timing
             te = tune_shapes(
-                key, PIC_FP32, b->stream,
+                key, PIC_FP32, false, b->stream,
                 [b](const LaunchShape &s) {
                     b->shape = s;
                     b->grid = b->cus * step_occupancy(s, b->cfg.ng_max, PIC_FP32);

@@ -1,7 +1,8 @@
 // Launch-shape autotuner of the particle pass.
 //
 // The particle pass is timed with HIP events for every candidate shape
-// (threads per workgroup x particle vectors per lane per iteration) on the
+// (threads per workgroup x particle vectors per lane per iteration, and for
+// single runs x the order in which workgroups take tiles) on the
 // caller's real state, five launches each, interleaved across candidates,
 // and scored by the median; the incumbent shape stays unless another is at
 // least 2% faster; the caller saves the particle arrays before and
@@ -45,7 +46,7 @@ void load_file_locked() {
         std::istringstream ls(line);
         std::string key;
         LaunchShape s;
-        if (ls >> key >> s.block >> s.unroll) g_cache[key] = s;
+        if (ls >> key >> s.block >> s.unroll >> s.order) g_cache[key] = s;
     }
 }
 
@@ -53,7 +54,7 @@ void append_file_locked(const std::string &key, const LaunchShape &s, double ms)
     const char *path = cache_path();
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << ' ' << s.block << ' ' << s.unroll << ' ' << ms << '\n';
+    out << key << ' ' << s.block << ' ' << s.unroll << ' ' << s.order << ' ' << ms << '\n';
 }
 
 int log2_ceil(int64_t v) {
@@ -90,28 +91,31 @@ bool tune_lookup(const std::string &key, LaunchShape *out) {
     return true;
 }
 
-hipError_t tune_shapes(const std::string &key, int precision, hipStream_t stream,
+hipError_t tune_shapes(const std::string &key, int precision, bool orders, hipStream_t stream,
                        const std::function<hipError_t(const LaunchShape &)> &prepare,
                        const std::function<hipError_t(const LaunchShape &)> &launch, LaunchShape *best) {
     // intermediate sizes: 640 threads fit two workgroups per CU at five
     // waves per SIMD, 768 one of twelve waves; each wins on some workloads
     static const int kBlocks[] = {256, 512, 640, 768, 1024};
     static const int kUnrolls[] = {1, 2, 4};
-    constexpr int kCand = 15;
+    constexpr int kMaxCand = 30;                      // x 2 tile orders (single runs)
     constexpr int kRounds = 5;
     // A challenger must beat the incumbent (the shape passed in) by this
     // fraction of its time: shapes within noise of each other do not flip
     // from one process to the next.
     constexpr double kMargin = 0.02;
-    LaunchShape cand[kCand];
+    LaunchShape cand[kMaxCand];
     int nc = 0;
-    for (int blk : kBlocks)
-        for (int un : kUnrolls) {
-            cand[nc].block = blk;
-            cand[nc].unroll = un;
-            ++nc;
-        }
-    hipEvent_t ev[2 * kCand] = {};
+    for (int ord = 0; ord < (orders ? 2 : 1); ++ord)
+        for (int blk : kBlocks)
+            for (int un : kUnrolls) {
+                cand[nc].block = blk;
+                cand[nc].unroll = un;
+                cand[nc].order = ord;
+                ++nc;
+            }
+    const int kCand = nc;
+    hipEvent_t ev[2 * kMaxCand] = {};
     hipError_t err = hipSuccess;
     for (int i = 0; i < 2 * kCand && err == hipSuccess; ++i) err = hipEventCreate(&ev[i]);
     std::vector<float> t((size_t)kCand * kRounds, 0.0f);
@@ -136,13 +140,14 @@ hipError_t tune_shapes(const std::string &key, int precision, hipStream_t stream
     for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
     if (err != hipSuccess) return err;
-    double med[kCand];
+    double med[kMaxCand];
     int incumbent = -1, fastest = 0;
     for (int c = 0; c < kCand; ++c) {
         std::vector<float> v(t.begin() + (long)c * kRounds, t.begin() + (long)(c + 1) * kRounds);
         std::sort(v.begin(), v.end());
         med[c] = v[kRounds / 2];
-        if (cand[c].block == best->block && cand[c].unroll == best->unroll) incumbent = c;
+        if (cand[c].block == best->block && cand[c].unroll == best->unroll && cand[c].order == best->order)
+            incumbent = c;
         if (med[c] < med[fastest]) fastest = c;
     }
     int pick = fastest;

@@ -397,13 +397,16 @@ def test_admission_under_a_small_budget_and_release():
 
 def test_results_do_not_depend_on_the_launch_shape(monkeypatch):
     """Tiles and summation orders are fixed by the run, so every launch shape
-    the autotuner may pick gives bit-identical state, grid and history."""
+    the autotuner may pick (threads, vectors per lane, and the order in which
+    workgroups take tiles) gives bit-identical state, grid and history."""
     spec = I.warm_two_stream_large(seed=21, np_=200_003, ng=256, nsteps=12, L=0.032 * 256)
     x, v = spec.particles()
     ref = None
-    for block, unroll in [(1024, 1), (512, 2), (256, 4), (1024, 4), (640, 1), (768, 2)]:
+    for block, unroll, order in [(1024, 1, 0), (512, 2, 1), (256, 4, 0), (1024, 4, 1), (640, 1, 1), (768, 2, 0),
+                                 (1024, 1, 1)]:
         monkeypatch.setenv("PIC1D_BLOCK", str(block))
         monkeypatch.setenv("PIC1D_UNROLL", str(unroll))
+        monkeypatch.setenv("PIC1D_TILE_ORDER", str(order))
         run, p = make_run(spec, history=spec.nsteps, x=x, v=v)
         with run:
             run.step(spec.nsteps)
