@@ -114,13 +114,13 @@ pic_status validate(const pic_params *p) {
 
 // Default particles per tile: a pure function of np, so that every launch
 // shape and schedule sees the same tiles (and the same diagnostic summation
-// order).  About 4096 tiles per run, so that a large single run gives the
-// device's wavefronts a tile each (one tile per wavefront at a time); at
-// least 2048 particles from 1M particles on (fewer per-tile start-ups when
-// many runs share the device), at least 1024 and at most 16384 (whole block
-// units).
+// order).  About 8192 tiles per run, so that a large single run gives the
+// device's wavefronts several tiles each (with the round-robin tile order
+// the autotuner can then pick, HBM serves the pass faster); at least 2048
+// particles from 1M particles on (fewer per-tile start-ups when many runs
+// share the device), at least 1024 and at most 16384 (whole block units).
 int default_tile(int64_t np) {
-    const int64_t per = (np + 4095) / 4096;
+    const int64_t per = (np + 8191) / 8192;
     int64_t t = (per + kUnit - 1) / kUnit * kUnit;
     t = std::max<int64_t>(t, np >= ((int64_t)1 << 20) ? 2 * kUnit : kUnit);
     return (int)std::min<int64_t>(16384, t);
