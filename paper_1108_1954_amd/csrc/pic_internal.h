@@ -80,7 +80,8 @@ struct WorkQueue {
 constexpr int kUnit = 1024;
 
 // Launch shape of the step kernel (chosen per run by the autotuner):
-// threads per workgroup and particle vectors per lane per iteration.
+// threads per workgroup, particle vectors per lane per iteration, the tile
+// order of single runs and the cache policy of the particle accesses.
 struct LaunchShape {
     int block = 512;
     int unroll = 2;
@@ -91,6 +92,10 @@ struct LaunchShape {
     // The tiles themselves, and so the results, are the same.  Batches use
     // their work list.
     int order = 0;
+    // 0: non-temporal particle loads and stores; 1: ordinary cached ones
+    // (faster when the particle state fits the last-level cache and stays
+    // there between steps).  Results are the same.
+    int cached = 0;
 };
 
 // Kernel launchers (pic_kernels.hip).  launch_step enqueues one step on

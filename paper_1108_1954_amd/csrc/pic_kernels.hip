@@ -41,15 +41,19 @@ template <typename T> struct Vec;
 template <> struct Vec<float> { using type = f32x4; static constexpr int n = 4; };
 template <> struct Vec<double> { using type = f64x2; static constexpr int n = 2; };
 
-// Streaming accesses to particle arrays: global address space, non-temporal
-// (each particle is touched once per step).
-template <typename V>
+// Streaming accesses to particle arrays, global address space.  NT marks
+// them non-temporal (each particle is touched once per step); without it they
+// are ordinary cached accesses, which let a particle state smaller than the
+// device's last-level cache stay there from one step to the next.
+template <typename V, bool NT>
 __device__ __forceinline__ V load_stream(const void *p) {
-    return __builtin_nontemporal_load((const GLOBAL_AS V *)p);
+    if constexpr (NT) return __builtin_nontemporal_load((const GLOBAL_AS V *)p);
+    else return *(const GLOBAL_AS V *)p;
 }
-template <typename V>
+template <typename V, bool NT>
 __device__ __forceinline__ void store_stream(void *p, V v) {
-    __builtin_nontemporal_store(v, (GLOBAL_AS V *)p);
+    if constexpr (NT) __builtin_nontemporal_store(v, (GLOBAL_AS V *)p);
+    else *(GLOBAL_AS V *)p = v;
 }
 
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -187,22 +191,22 @@ __device__ __forceinline__ void fill_table(const T *tab, T *Et, int ng) {
 
 // Issue the loads of one block: UNROLL vectors of VEC particles per lane,
 // lane-contiguous so each load instruction covers 64*VEC particles.
-template <typename V, int VEC, int UNROLL>
+template <typename V, int VEC, int UNROLL, bool NT>
 __device__ __forceinline__ void load_block(const void *U, const void *W, int64_t base, int lane,
                                            V (&u)[UNROLL], V (&w)[UNROLL]) {
     using T = decltype(u[0][0] + 0);
 #pragma unroll
     for (int k = 0; k < UNROLL; ++k) {
         const int64_t i = base + (int64_t)(k * 64 + lane) * VEC;
-        u[k] = load_stream<V>((const T *)U + i);
-        w[k] = load_stream<V>((const T *)W + i);
+        u[k] = load_stream<V, NT>((const T *)U + i);
+        w[k] = load_stream<V, NT>((const T *)W + i);
     }
 }
 
 // Push and deposit one loaded block, then store it back.  All gathers of the
 // block are issued first (one LDS wait per block), then the pushes, deposits
 // and stores; the accumulation order per lane is the particle order.
-template <typename T, typename V, int VEC, int UNROLL, bool PUSH>
+template <typename T, typename V, int VEC, int UNROLL, bool PUSH, bool NT>
 __device__ __forceinline__ void run_block(void *U, void *W, int64_t base, int lane, V (&u)[UNROLL],
                                           V (&w)[UNROLL], const T *Et, unsigned long long *Sl, int ng,
                                           T ngf, T hi, double &a1, double &a2, uint32_t &flags) {
@@ -231,8 +235,8 @@ __device__ __forceinline__ void run_block(void *U, void *W, int64_t base, int la
 #pragma unroll
         for (int k = 0; k < UNROLL; ++k) {
             const int64_t i = base + (int64_t)(k * 64 + lane) * VEC;
-            store_stream<V>((T *)U + i, u[k]);
-            store_stream<V>((T *)W + i, w[k]);
+            store_stream<V, NT>((T *)U + i, u[k]);
+            store_stream<V, NT>((T *)W + i, w[k]);
         }
     }
 }
@@ -260,7 +264,7 @@ __device__ __forceinline__ void run_one(T *U, T *W, int64_t q, const T *Et, unsi
 // tile partial sums depend only on the run.  The deposits stay in the
 // private grid Sl (merged by the caller); the gather table is loaded into Et
 // only when `load_table` (the previous chunk was of another run).
-template <typename T, int BLOCK, int UNROLL, bool PUSH>
+template <typename T, int BLOCK, int UNROLL, bool PUSH, bool NT>
 __device__ void process_chunk(RunDev *R, int tb, int te, int tstride, bool load_table, unsigned long long *Sl,
                               T *Et, int *next_tile) {
     using V = typename Vec<T>::type;
@@ -269,7 +273,7 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int tstride, bool load_
     constexpr int SPB = kUnit / PER;                 // sub-blocks per block unit
     static_assert(kUnit % PER == 0, "a block unit holds whole sub-blocks");
     // Register sets in the load pipeline: three at one vector per lane
-    // (84 VGPRs, five waves per SIMD), two when the sub-blocks are wider
+    // (95 VGPRs, five waves per SIMD), two when the sub-blocks are wider
     // (a third measured no faster and spills at 1024 threads).  Four sets
     // at one vector cost a wave per SIMD and measured slower.
     constexpr int DEPTH = UNROLL == 1 ? 3 : 2;
@@ -311,7 +315,7 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int tstride, bool load_
         if (nb > 0) {
 #pragma unroll
             for (int d = 0; d < DEPTH - 1; ++d)
-                load_block<V, VEC, UNROLL>(U, W, sub(min((int64_t)d, nb - 1)), lane, bu[d], bw[d]);
+                load_block<V, VEC, UNROLL, NT>(U, W, sub(min((int64_t)d, nb - 1)), lane, bu[d], bw[d]);
         }
         const int64_t nrounds = nb / DEPTH;
         for (int64_t q = 0; q < nrounds; ++q) {
@@ -319,18 +323,18 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int tstride, bool load_
             for (int d = 0; d < DEPTH; ++d) {
                 const int64_t ahead = q * DEPTH + d + DEPTH - 1;
                 if (ahead < nb)
-                    load_block<V, VEC, UNROLL>(U, W, sub(ahead), lane, bu[(d + DEPTH - 1) % DEPTH],
-                                               bw[(d + DEPTH - 1) % DEPTH]);
-                run_block<T, V, VEC, UNROLL, PUSH>(U, W, sub(q * DEPTH + d), lane, bu[d], bw[d], Et, Sl, ng, ngf,
-                                                   hi, a1, a2, flags);
+                    load_block<V, VEC, UNROLL, NT>(U, W, sub(ahead), lane, bu[(d + DEPTH - 1) % DEPTH],
+                                                   bw[(d + DEPTH - 1) % DEPTH]);
+                run_block<T, V, VEC, UNROLL, PUSH, NT>(U, W, sub(q * DEPTH + d), lane, bu[d], bw[d], Et, Sl, ng,
+                                                       ngf, hi, a1, a2, flags);
             }
         }
         const int64_t rest = nb - nrounds * DEPTH;
 #pragma unroll
         for (int d = 0; d < DEPTH - 1; ++d)
             if (d < rest)
-                run_block<T, V, VEC, UNROLL, PUSH>(U, W, sub(nrounds * DEPTH + d), lane, bu[d], bw[d], Et, Sl, ng,
-                                                   ngf, hi, a1, a2, flags);
+                run_block<T, V, VEC, UNROLL, PUSH, NT>(U, W, sub(nrounds * DEPTH + d), lane, bu[d], bw[d], Et, Sl,
+                                                       ng, ngf, hi, a1, a2, flags);
         // The run's partial last unit belongs to tile nfull mod ntiles: same
         // per-lane order as a full unit; whole vectors where they fit, then
         // single particles.
@@ -340,10 +344,10 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int tstride, bool load_
                     const int64_t i = base + (int64_t)(k * 64 + lane) * VEC;
                     if (i + VEC <= np) {
                         V vu[1], vw[1];
-                        vu[0] = load_stream<V>(U + i);
-                        vw[0] = load_stream<V>(W + i);
-                        run_block<T, V, VEC, 1, PUSH>(U, W, i - (int64_t)lane * VEC, lane, vu, vw, Et, Sl, ng,
-                                                      ngf, hi, a1, a2, flags);
+                        vu[0] = load_stream<V, NT>(U + i);
+                        vw[0] = load_stream<V, NT>(W + i);
+                        run_block<T, V, VEC, 1, PUSH, NT>(U, W, i - (int64_t)lane * VEC, lane, vu, vw, Et, Sl, ng,
+                                                          ngf, hi, a1, a2, flags);
                     } else {
                         for (int e = 0; e < VEC; ++e) {
                             const int64_t q = i + e;
@@ -400,7 +404,7 @@ __device__ void merge_grid(unsigned long long *S, int ng, int rot_seed, unsigned
 // computes it (per-tile partials, integer grid sums).  A workgroup merges
 // its private grid when it moves to another run and when it is done, so
 // chunks of one run in a row cost one table load and one merge.
-template <typename T, int BLOCK, int UNROLL, bool PUSH>
+template <typename T, int BLOCK, int UNROLL, bool PUSH, bool NT>
 __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkItem *items, WorkQueue *queue,
                                                     int ng_lds, int order) {
     extern __shared__ unsigned long long lds[];
@@ -474,7 +478,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
                     ng_pend = ngr;
                     rot_pend = chunk;
                 }
-                process_chunk<T, BLOCK, UNROLL, PUSH>(R, tb, te, tstride, r != prev_run, Sl, Et, &s_tile);
+                process_chunk<T, BLOCK, UNROLL, PUSH, NT>(R, tb, te, tstride, r != prev_run, Sl, Et, &s_tile);
                 prev_run = r;
             }
             const int g1 = (int)((int64_t)ngr * (chunk + 1) / nchunks);
@@ -486,42 +490,51 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
 }
 
 
+// The prologue (initial deposit, no stores) always reads non-temporally.
 template <typename T, int BLOCK, int UNROLL, bool PUSH>
-const void *kernel_ptr() {
-    return (const void *)step_kernel<T, BLOCK, UNROLL, PUSH>;
+const void *kernel_ptr(bool cached) {
+    if constexpr (!PUSH) {
+        (void)cached;
+        return (const void *)step_kernel<T, BLOCK, UNROLL, PUSH, true>;
+    } else {
+        return cached ? (const void *)step_kernel<T, BLOCK, UNROLL, PUSH, false>
+                      : (const void *)step_kernel<T, BLOCK, UNROLL, PUSH, true>;
+    }
 }
 
 template <typename T, int BLOCK, bool PUSH>
-const void *kernel_unroll(int unroll) {
+const void *kernel_unroll(int unroll, bool cached) {
     if constexpr (!PUSH) {
         (void)unroll;
-        return kernel_ptr<T, BLOCK, 1, PUSH>();
+        return kernel_ptr<T, BLOCK, 1, PUSH>(cached);
     } else {
         switch (unroll) {
-            case 1: return kernel_ptr<T, BLOCK, 1, PUSH>();
-            case 2: return kernel_ptr<T, BLOCK, 2, PUSH>();
-            case 4: return kernel_ptr<T, BLOCK, 4, PUSH>();
+            case 1: return kernel_ptr<T, BLOCK, 1, PUSH>(cached);
+            case 2: return kernel_ptr<T, BLOCK, 2, PUSH>(cached);
+            case 4: return kernel_ptr<T, BLOCK, 4, PUSH>(cached);
             default: return nullptr;
         }
     }
 }
 
 template <typename T, bool PUSH>
-const void *kernel_for(int block, int unroll) {
+const void *kernel_for(int block, int unroll, bool cached) {
     switch (block) {
-        case 256: return kernel_unroll<T, 256, PUSH>(unroll);
-        case 512: return kernel_unroll<T, 512, PUSH>(unroll);
-        case 640: return kernel_unroll<T, 640, PUSH>(unroll);
-        case 768: return kernel_unroll<T, 768, PUSH>(unroll);
-        case 1024: return kernel_unroll<T, 1024, PUSH>(unroll);
+        case 256: return kernel_unroll<T, 256, PUSH>(unroll, cached);
+        case 512: return kernel_unroll<T, 512, PUSH>(unroll, cached);
+        case 640: return kernel_unroll<T, 640, PUSH>(unroll, cached);
+        case 768: return kernel_unroll<T, 768, PUSH>(unroll, cached);
+        case 1024: return kernel_unroll<T, 1024, PUSH>(unroll, cached);
         default: return nullptr;
     }
 }
 
 const void *kernel_select(const LaunchShape &ls, int precision, bool push) {
+    if (ls.cached != 0 && ls.cached != 1) return nullptr;
+    const bool c = ls.cached != 0;
     if (precision == 0)
-        return push ? kernel_for<float, true>(ls.block, ls.unroll) : kernel_for<float, false>(ls.block, 1);
-    return push ? kernel_for<double, true>(ls.block, ls.unroll) : kernel_for<double, false>(ls.block, 1);
+        return push ? kernel_for<float, true>(ls.block, ls.unroll, c) : kernel_for<float, false>(ls.block, 1, c);
+    return push ? kernel_for<double, true>(ls.block, ls.unroll, c) : kernel_for<double, false>(ls.block, 1, c);
 }
 
 }  // namespace

@@ -53,7 +53,7 @@ namespace {
 struct DeviceInfo {
     int cus = 256;
     LaunchShape shape;     // default launch shape
-    bool forced = false;   // shape set through PIC1D_BLOCK / PIC1D_UNROLL / PIC1D_TILE_ORDER
+    bool forced = false;   // shape set through PIC1D_BLOCK / PIC1D_UNROLL / PIC1D_TILE_ORDER / PIC1D_CACHED
     bool autotune = true;  // PIC1D_AUTOTUNE=0 turns the autotuner off
 };
 
@@ -83,6 +83,10 @@ DeviceInfo device_info() {
     }
     if (const char *o = getenv("PIC1D_TILE_ORDER")) {
         d.shape.order = atoi(o) != 0 ? 1 : 0;
+        d.forced = true;
+    }
+    if (const char *c = getenv("PIC1D_CACHED")) {
+        d.shape.cached = atoi(c) != 0 ? 1 : 0;
         d.forced = true;
     }
     if (const char *a = getenv("PIC1D_AUTOTUNE")) d.autotune = atoi(a) != 0;

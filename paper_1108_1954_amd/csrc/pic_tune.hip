@@ -1,10 +1,13 @@
 // Launch-shape autotuner of the particle pass.
 //
 // The particle pass is timed with HIP events for every candidate shape
-// (threads per workgroup x particle vectors per lane per iteration, and for
-// single runs x the order in which workgroups take tiles) on the
-// caller's real state, five launches each, interleaved across candidates,
-// and scored by the median; the incumbent shape stays unless another is at
+// (threads per workgroup x particle vectors per lane per iteration x the
+// cache policy of the particle accesses, and for single runs x the order in
+// which workgroups take tiles) on the caller's real state, five launches
+// each, interleaved across candidates, each timed launch right after an
+// untimed one of the same candidate (so a cached candidate finds the caches
+// as its own steps leave them), and scored by the median; the incumbent
+// shape stays unless another is at
 // least 2% faster; the caller saves the particle arrays before and
 // restores them after, so tuning leaves no trace in the results (which do
 // not depend on the shape in any case: tiles and summation orders are fixed
@@ -43,10 +46,13 @@ void load_file_locked() {
     std::ifstream in(path);
     std::string line;
     while (std::getline(in, line)) {
+        // key block unroll order cached ms: lines of another form are skipped
         std::istringstream ls(line);
-        std::string key;
+        std::string key, extra;
         LaunchShape s;
-        if (ls >> key >> s.block >> s.unroll >> s.order) g_cache[key] = s;
+        double ms = 0;
+        if ((ls >> key >> s.block >> s.unroll >> s.order >> s.cached >> ms) && !(ls >> extra))
+            g_cache[key] = s;
     }
 }
 
@@ -54,7 +60,7 @@ void append_file_locked(const std::string &key, const LaunchShape &s, double ms)
     const char *path = cache_path();
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << ' ' << s.block << ' ' << s.unroll << ' ' << s.order << ' ' << ms << '\n';
+    out << key << ' ' << s.block << ' ' << s.unroll << ' ' << s.order << ' ' << s.cached << ' ' << ms << '\n';
 }
 
 int log2_ceil(int64_t v) {
@@ -98,7 +104,7 @@ hipError_t tune_shapes(const std::string &key, int precision, bool orders, hipSt
     // waves per SIMD, 768 one of twelve waves; each wins on some workloads
     static const int kBlocks[] = {256, 512, 640, 768, 1024};
     static const int kUnrolls[] = {1, 2, 4};
-    constexpr int kMaxCand = 30;                      // x 2 tile orders (single runs)
+    constexpr int kMaxCand = 60;                      // x 2 cache policies x 2 tile orders (single runs)
     constexpr int kRounds = 5;
     // A challenger must beat the incumbent (the shape passed in) by this
     // fraction of its time: shapes within noise of each other do not flip
@@ -106,26 +112,30 @@ hipError_t tune_shapes(const std::string &key, int precision, bool orders, hipSt
     constexpr double kMargin = 0.02;
     LaunchShape cand[kMaxCand];
     int nc = 0;
-    for (int ord = 0; ord < (orders ? 2 : 1); ++ord)
-        for (int blk : kBlocks)
-            for (int un : kUnrolls) {
-                cand[nc].block = blk;
-                cand[nc].unroll = un;
-                cand[nc].order = ord;
-                ++nc;
-            }
+    for (int cached = 0; cached < 2; ++cached)
+        for (int ord = 0; ord < (orders ? 2 : 1); ++ord)
+            for (int blk : kBlocks)
+                for (int un : kUnrolls) {
+                    cand[nc].block = blk;
+                    cand[nc].unroll = un;
+                    cand[nc].order = ord;
+                    cand[nc].cached = cached;
+                    ++nc;
+                }
     const int kCand = nc;
     hipEvent_t ev[2 * kMaxCand] = {};
     hipError_t err = hipSuccess;
     for (int i = 0; i < 2 * kCand && err == hipSuccess; ++i) err = hipEventCreate(&ev[i]);
     std::vector<float> t((size_t)kCand * kRounds, 0.0f);
-    // round 0 warms every candidate up; rounds 1..kRounds are timed, each
-    // launch on its own and the candidates interleaved, so that drift of the
-    // device's clocks affects them alike; prepare() runs outside the timing
+    // round 0 warms every candidate up; in rounds 1..kRounds the second of
+    // each candidate's two launches is timed, on its own, the candidates
+    // interleaved so that drift of the device's clocks affects them alike;
+    // prepare() runs outside the timing
     for (int round = 0; round <= kRounds && err == hipSuccess; ++round) {
         for (int c = 0; c < kCand && err == hipSuccess; ++c) {
             if ((err = step_prepare(cand[c], precision)) != hipSuccess) break;
             if ((err = prepare(cand[c])) != hipSuccess) break;
+            if ((err = launch(cand[c])) != hipSuccess) break;
             if (round > 0 && (err = hipEventRecord(ev[2 * c], stream)) != hipSuccess) break;
             if ((err = launch(cand[c])) != hipSuccess) break;
             if (round > 0 && (err = hipEventRecord(ev[2 * c + 1], stream)) != hipSuccess) break;
@@ -146,7 +156,8 @@ hipError_t tune_shapes(const std::string &key, int precision, bool orders, hipSt
         std::vector<float> v(t.begin() + (long)c * kRounds, t.begin() + (long)(c + 1) * kRounds);
         std::sort(v.begin(), v.end());
         med[c] = v[kRounds / 2];
-        if (cand[c].block == best->block && cand[c].unroll == best->unroll && cand[c].order == best->order)
+        if (cand[c].block == best->block && cand[c].unroll == best->unroll && cand[c].order == best->order &&
+            cand[c].cached == best->cached)
             incumbent = c;
         if (med[c] < med[fastest]) fastest = c;
     }

@@ -283,9 +283,13 @@ def small_ensemble(n, seed=3):
     return runs
 
 
-def test_batched_runs_equal_the_same_runs_alone():
+@pytest.mark.parametrize("cached", [None, "1"])
+def test_batched_runs_equal_the_same_runs_alone(monkeypatch, cached):
     """Six runs of different (np, ng <= 2048) in one batch: state, grids and
-    history equal each run stepped alone, bit for bit."""
+    history equal each run stepped alone, bit for bit (shapes as tuned, and
+    with cached particle accesses forced on both sides)."""
+    if cached is not None:
+        monkeypatch.setenv("PIC1D_CACHED", cached)
     specs = small_ensemble(6)
     parts = [s.particles() for s in specs]
     alone = []
@@ -397,16 +401,18 @@ def test_admission_under_a_small_budget_and_release():
 
 def test_results_do_not_depend_on_the_launch_shape(monkeypatch):
     """Tiles and summation orders are fixed by the run, so every launch shape
-    the autotuner may pick (threads, vectors per lane, and the order in which
-    workgroups take tiles) gives bit-identical state, grid and history."""
+    the autotuner may pick (threads, vectors per lane, the order in which
+    workgroups take tiles, non-temporal or cached particle accesses) gives
+    bit-identical state, grid and history."""
     spec = I.warm_two_stream_large(seed=21, np_=200_003, ng=256, nsteps=12, L=0.032 * 256)
     x, v = spec.particles()
     ref = None
-    for block, unroll, order in [(1024, 1, 0), (512, 2, 1), (256, 4, 0), (1024, 4, 1), (640, 1, 1), (768, 2, 0),
-                                 (1024, 1, 1)]:
+    for block, unroll, order, cached in [(1024, 1, 0, 0), (512, 2, 1, 1), (256, 4, 0, 1), (1024, 4, 1, 0),
+                                         (640, 1, 1, 1), (768, 2, 0, 0), (1024, 1, 1, 1), (1024, 1, 0, 1)]:
         monkeypatch.setenv("PIC1D_BLOCK", str(block))
         monkeypatch.setenv("PIC1D_UNROLL", str(unroll))
         monkeypatch.setenv("PIC1D_TILE_ORDER", str(order))
+        monkeypatch.setenv("PIC1D_CACHED", str(cached))
         run, p = make_run(spec, history=spec.nsteps, x=x, v=v)
         with run:
             run.step(spec.nsteps)
