@@ -233,14 +233,20 @@ def workload_probe(args, P, torch, nbytes=2 << 30):
     ms = P.pic_bandwidth_probe(a.data_ptr(), b.data_ptr(), n, reps=args.steps, stream=P.current_stream())
     # The same swap over exactly the state of each workload's particle pass
     # (one launch per swap, as one pass is one launch): the achievable rate
-    # for that many bytes, launch ramp and tail included.
+    # for that many bytes, launch ramp and tail included, with non-temporal
+    # and with cached accesses (the pass's two cache policies; a state that
+    # fits the last-level cache stays there between launches).
     sized = {}
     for name, npart in (("serving batch of 8 runs", 1_804_773), ("paper workload", 8_192_000),
                         ("single run 2^26", 1 << 26), ("ensemble", 145_439_881)):
         m = npart // 4 * 4
-        t = P.pic_bandwidth_probe(a.data_ptr(), b.data_ptr(), m, reps=max(args.steps, 50),
-                                  stream=P.current_stream())
-        sized[name] = {"particles": m, "bytes": 16 * m, "swap_us": 1e3 * t, "GBps": 16 * m / (t * 1e6)}
+        row = {"particles": m, "bytes": 16 * m}
+        for key, cached in (("", False), ("cached_", True)):
+            t = P.pic_bandwidth_probe(a.data_ptr(), b.data_ptr(), m, reps=max(args.steps, 50),
+                                      stream=P.current_stream(), cached=cached)
+            row[key + "swap_us"] = 1e3 * t
+            row[key + "GBps"] = 16 * m / (t * 1e6)
+        sized[name] = row
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)

@@ -226,12 +226,16 @@ pic_status pic_step_profiled(pic_run *run, int64_t nsteps, double *ms_particle, 
 /* Achievable-bandwidth reference of the particle pass (measurement only, no
  * part of the method): swaps the contents of the device arrays a[n] and
  * b[n] of FP32 values, `reps` >= 1 times on `stream`, with the pass's memory
- * pattern (16-byte non-temporal loads and stores, all CUs) and nothing
+ * pattern (16-byte loads and stores, all CUs; cached = 0: non-temporal,
+ * 1: ordinary cached accesses, the pass's two cache policies) and nothing
  * else, i.e. 16 bytes per element pair per swap, and reports the mean
- * duration of one swap in milliseconds (HIP events; waits for them).
+ * duration of one swap in milliseconds (HIP events around the `reps`
+ * back-to-back launches, after one warm-up launch; waits for them).
  * a and b are caller-owned device buffers, 16-byte aligned, n a multiple
- * of 4 (else EINVAL); their contents end swapped if reps is odd. */
-pic_status pic_bandwidth_probe(void *a, void *b, int64_t n, int32_t reps, void *stream, double *ms);
+ * of 4, cached 0 or 1 (else EINVAL); their contents end swapped if reps is
+ * even (reps + 1 launches). */
+pic_status pic_bandwidth_probe(void *a, void *b, int64_t n, int32_t reps, int32_t cached, void *stream,
+                               double *ms);
 
 /* Synchronise the run's stream and report diagnostics of the current state.
  * rho_out/E_out (FP64, ng_cap >= ng entries) may be NULL. */

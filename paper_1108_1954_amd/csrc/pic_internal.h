@@ -55,14 +55,17 @@ struct RunDev {
 };
 
 // One unit of schedule: tiles [tile_begin, tile_end) of run `run`, which is
-// chunk `chunk` of the run's `nchunks` chunks in this launch.
+// chunk `chunk` of the run's `nchunks` chunks in this launch; `ng` and
+// `table` repeat the run's grid size and gather-table address (fixed for the
+// run's life) so the pass can load the table without the run descriptor.
 struct WorkItem {
     int32_t run;
     int32_t tile_begin;
     int32_t tile_end;
     int32_t chunk;
     int32_t nchunks;
-    int32_t pad_;
+    int32_t ng;
+    const void *table;
 };
 
 // Work queue of a batched particle pass (device memory): workgroup b takes
@@ -101,8 +104,10 @@ struct LaunchShape {
 // Kernel launchers (pic_kernels.hip).  launch_step enqueues one step on
 // `stream` as two launches: the particle pass, then the field solve.
 //   items == nullptr: single run `runs[0]`, tiles split over `grid`
-//   workgroups in the shape's tile order.  Otherwise the workgroups take items[0 .. queue->nitems)
-//   through the queue.
+//   workgroups in the shape's tile order, `table` its gather table (Ehat,
+//   or Ehat64 for the FP64 state; may be null for the prologue) and ng_lds
+//   its ng.  Otherwise the workgroups take items[0 .. queue->nitems)
+//   through the queue (`table` unused).
 //   The solve launch has nsolve workgroups; workgroup b solves
 //   runs[slots[b]] (slots == nullptr: runs[b]); a slot of -1, idle and
 //   finished runs return at once.
@@ -112,7 +117,7 @@ struct LaunchShape {
 struct StepEvents {
     hipEvent_t e0, e1, e2;
 };
-hipError_t launch_step(RunDev *runs, const WorkItem *items, WorkQueue *queue,
+hipError_t launch_step(RunDev *runs, const WorkItem *items, WorkQueue *queue, const void *table,
                        int grid, const LaunchShape &shape, int ng_lds, int precision, int prologue,
                        const int32_t *slots, int nsolve, hipStream_t stream, const StepEvents *ev = nullptr);
 
@@ -123,7 +128,7 @@ hipError_t launch_solve(RunDev *runs, const int32_t *slots, int nsolve, int prol
                         hipStream_t stream);
 
 // The particle pass alone (used by the autotuner on saved state).
-hipError_t launch_particles(RunDev *runs, const WorkItem *items, WorkQueue *queue,
+hipError_t launch_particles(RunDev *runs, const WorkItem *items, WorkQueue *queue, const void *table,
                             int grid, const LaunchShape &shape, int ng_lds, int precision,
                             int prologue, hipStream_t stream);
 
@@ -184,7 +189,7 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream);
 
 // Bandwidth reference (pic_probe.hip): swap two device arrays of nvec
 // 16-byte vectors (the particle pass's bytes, nothing else).
-hipError_t launch_swap(void *a, void *b, int64_t nvec, int cus, hipStream_t stream);
+hipError_t launch_swap(void *a, void *b, int64_t nvec, int cus, bool cached, hipStream_t stream);
 
 // Autotuner (pic_tune.hip).  tune_key names a size class; tune_lookup finds
 // a cached shape; tune_shapes times `launch(shape)` (one particle pass on

@@ -64,13 +64,6 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 __device__ __forceinline__ uint32_t frac32(float f) { return (uint32_t)(f * 4294967296.0f); }
 __device__ __forceinline__ uint32_t frac32(double f) { return (uint32_t)(f * 4294967296.0); }
 
-template <typename T> __device__ __forceinline__ const T *gather_table(const RunDev *R);
-template <> __device__ __forceinline__ const float *gather_table<float>(const RunDev *R) {
-    return R->Ehat;
-}
-template <> __device__ __forceinline__ const double *gather_table<double>(const RunDev *R) {
-    return R->Ehat64;
-}
 
 // Per-particle stages.  Conventions:
 //   s, w : stored position (x/dx + 1/2) and velocity w = v dt/dx
@@ -262,11 +255,11 @@ __device__ __forceinline__ void run_one(T *U, T *W, int64_t q, const T *Et, unsi
 // of VEC particles per iteration, all loads issued before any compute; a
 // lane's particles are accumulated in index order for every UNROLL, so the
 // tile partial sums depend only on the run.  The deposits stay in the
-// private grid Sl (merged by the caller); the gather table is loaded into Et
-// only when `load_table` (the previous chunk was of another run).
+// private grid Sl (merged by the caller); the caller has put the run's gather
+// table into Et (the barrier below orders it before every gather).
 template <typename T, int BLOCK, int UNROLL, bool PUSH, bool NT>
-__device__ void process_chunk(RunDev *R, int tb, int te, int tstride, bool load_table, unsigned long long *Sl,
-                              T *Et, int *next_tile) {
+__device__ void process_chunk(RunDev *R, int tb, int te, int tstride, unsigned long long *Sl, T *Et,
+                              int *next_tile) {
     using V = typename Vec<T>::type;
     constexpr int VEC = Vec<T>::n;
     constexpr int PER = 64 * VEC * UNROLL;
@@ -285,7 +278,6 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int tstride, bool load_
     double *part = R->tile_part;
     const T ngf = (T)ng;
     const T hi = ngf + T(0.5);
-    if (PUSH && load_table) fill_table<T, BLOCK>(gather_table<T>(R), Et, ng);
     if (threadIdx.x == 0) *next_tile = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -406,7 +398,7 @@ __device__ void merge_grid(unsigned long long *S, int ng, int rot_seed, unsigned
 // chunks of one run in a row cost one table load and one merge.
 template <typename T, int BLOCK, int UNROLL, bool PUSH, bool NT>
 __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkItem *items, WorkQueue *queue,
-                                                    int ng_lds, int order) {
+                                                    int ng_lds, int order, const T *table0) {
     extern __shared__ unsigned long long lds[];
     __shared__ uint32_t s_item;
     __shared__ int s_tile;
@@ -416,6 +408,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
     const uint32_t nitems = items ? queue->nitems : 1u;
     const uint32_t grid = gridDim.x;
     int prev_run = -1;
+    int table_run = -1;                               // the run whose gather table Et holds
     unsigned long long *S_pend = nullptr;             // grid of prev_run, merged when the run changes
     int ng_pend = 0, rot_pend = 0;
     for (uint32_t round = 0;; ++round) {
@@ -439,7 +432,8 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
             __syncthreads();                          // s_item is rewritten next round
         }
         if (it >= nitems) break;
-        int r = 0, tb, te, chunk, nchunks, tstride = 1;
+        int r = 0, tb, te, chunk, nchunks, tstride = 1, ngt;
+        const T *tab;
         if (items) {
             const WorkItem wi = items[it];
             r = wi.run;
@@ -447,7 +441,11 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
             te = wi.tile_end;
             chunk = wi.chunk;
             nchunks = wi.nchunks;
+            ngt = wi.ng;
+            tab = (const T *)wi.table;
         } else {
+            ngt = ng_lds;
+            tab = table0;
             const int64_t nt = runs[0].ntiles;
             if (order) {                              // tiles b, b + grid, b + 2 grid, ...
                 tb = blockIdx.x;
@@ -459,6 +457,14 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
             }
             chunk = blockIdx.x;
             nchunks = gridDim.x;
+        }
+        // The gather table's address and size come with the item (or the
+        // launch), so its loads start at once, beside those of the run
+        // descriptor below instead of after them.  Consecutive fills are
+        // separated by the barriers of the queue (or of process_chunk).
+        if (PUSH && r != table_run && ngt <= ng_lds) {
+            fill_table<T, BLOCK>(tab, Et, ngt);
+            table_run = r;
         }
         RunDev *R = runs + r;
         // the prologue (initial deposit) runs whatever the step target, even 0
@@ -478,7 +484,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
                     ng_pend = ngr;
                     rot_pend = chunk;
                 }
-                process_chunk<T, BLOCK, UNROLL, PUSH, NT>(R, tb, te, tstride, r != prev_run, Sl, Et, &s_tile);
+                process_chunk<T, BLOCK, UNROLL, PUSH, NT>(R, tb, te, tstride, Sl, Et, &s_tile);
                 prev_run = r;
             }
             const int g1 = (int)((int64_t)ngr * (chunk + 1) / nchunks);
@@ -555,25 +561,26 @@ hipError_t step_prepare(const LaunchShape &ls, int precision) {
     return hipSuccess;
 }
 
-hipError_t launch_particles(RunDev *runs, const WorkItem *items, WorkQueue *queue, int grid,
+hipError_t launch_particles(RunDev *runs, const WorkItem *items, WorkQueue *queue, const void *table, int grid,
                             const LaunchShape &ls, int ng_lds, int precision, int prologue,
                             hipStream_t stream) {
     if (grid <= 0 || ng_lds <= 0 || ng_lds > kMaxNg || (items && !queue)) return hipErrorInvalidValue;
+    if (!items && !table && prologue == 0) return hipErrorInvalidValue;
     const void *fn = kernel_select(ls, precision, prologue == 0);
     if (!fn) return hipErrorInvalidValue;
     int order = ls.order;
-    void *args[] = {(void *)&runs, (void *)&items, (void *)&queue, (void *)&ng_lds, (void *)&order};
+    void *args[] = {(void *)&runs, (void *)&items, (void *)&queue, (void *)&ng_lds, (void *)&order, (void *)&table};
     return hipLaunchKernel(fn, dim3(grid), dim3(ls.block), args, step_lds_bytes(precision, ng_lds),
                            stream);
 }
 
-hipError_t launch_step(RunDev *runs, const WorkItem *items, WorkQueue *queue, int grid,
+hipError_t launch_step(RunDev *runs, const WorkItem *items, WorkQueue *queue, const void *table, int grid,
                        const LaunchShape &ls, int ng_lds, int precision, int prologue, const int32_t *slots,
                        int nsolve, hipStream_t stream, const StepEvents *ev) {
     if (nsolve <= 0) return hipErrorInvalidValue;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev->e0, stream)) != hipSuccess) return e;
-    e = launch_particles(runs, items, queue, grid, ls, ng_lds, precision, prologue, stream);
+    e = launch_particles(runs, items, queue, table, grid, ls, ng_lds, precision, prologue, stream);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev->e1, stream)) != hipSuccess) return e;
     e = launch_solve(runs, slots, nsolve, prologue, ng_lds, stream);

@@ -206,6 +206,13 @@ struct pic_run {
     int graph_steps = 0;
 };
 
+// The run's gather table in its state precision (fixed for the run's life:
+// the cell sort moves particles, not the field), passed to the particle pass
+// so that it loads the table without waiting for the run descriptor.
+const void *gather_table_of(const pic_run *r) {
+    return r->p.precision ? (const void *)r->host.Ehat64 : (const void *)r->host.Ehat;
+}
+
 extern "C" pic_status pic_footprint(const pic_params *params, size_t *bytes) {
     pic_status st = validate(params);
     if (st != PIC_OK) return st;
@@ -358,7 +365,7 @@ pic_status queue_device_init(pic_run *r, const RunDev *desc) {
     HIP_TRY(hipMemsetAsync(r->host.tile_part, 0, (size_t)r->lay.ntiles * kPartCols * 8, r->stream));
     HIP_TRY(hipMemcpyAsync(r->dev, desc, sizeof(RunDev), hipMemcpyHostToDevice, r->stream));
     HIP_TRY(step_prepare(r->shape, r->p.precision));
-    HIP_TRY(launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng, r->p.precision, 1, nullptr,
+    HIP_TRY(launch_step(r->dev, nullptr, nullptr, gather_table_of(r), r->grid, r->shape, r->p.ng, r->p.precision, 1, nullptr,
                         1, r->stream));
     return PIC_OK;
 }
@@ -427,7 +434,7 @@ pic_status choose_shape(pic_run *r, const DeviceInfo &d) {
                 te = tune_shapes(
                     key, r->p.precision, true, r->stream, [](const LaunchShape &) { return hipSuccess; },
                     [r, cus](const LaunchShape &s) {
-                        return launch_particles(r->dev, nullptr, nullptr, single_run_grid(r, s, cus), s, r->p.ng,
+                        return launch_particles(r->dev, nullptr, nullptr, gather_table_of(r), single_run_grid(r, s, cus), s, r->p.ng,
                                                 r->p.precision, 0, r->stream);
                     },
                     &shape);
@@ -463,7 +470,7 @@ pic_status choose_sort_period(pic_run *r) {
     for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
     pic_status st = e == hipSuccess ? save_particles(r, tmp, false) : PIC_OK;
     auto pass = [r]() {
-        return launch_particles(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng, r->p.precision, 0,
+        return launch_particles(r->dev, nullptr, nullptr, gather_table_of(r), r->grid, r->shape, r->p.ng, r->p.precision, 0,
                                 r->stream);
     };
     float t_u = 0, t_sort = 0, t_s = 0;
@@ -670,7 +677,7 @@ pic_status enqueue_step(pic_run *r, const StepEvents *ev = nullptr) {
         if (e == hipSuccess) r->swapped = !r->swapped;
     }
     if (e == hipSuccess)
-        e = launch_step(r->dev, nullptr, nullptr, r->grid, r->shape, r->p.ng, r->p.precision, 0, nullptr, 1,
+        e = launch_step(r->dev, nullptr, nullptr, gather_table_of(r), r->grid, r->shape, r->p.ng, r->p.precision, 0, nullptr, 1,
                         r->stream, ev);
     if (e != hipSuccess) {
         r->error = true;
@@ -730,7 +737,7 @@ extern "C" pic_status pic_step_graph(pic_run *r, int64_t nsteps, int32_t graph_s
     // steps.  A graph is replayed only where no sort falls inside it.
     const pic_run *rc = r;
     auto step_launch = [rc](hipStream_t s) {
-        return launch_step(rc->dev, nullptr, nullptr, rc->grid, rc->shape, rc->p.ng, rc->p.precision, 0, nullptr, 1,
+        return launch_step(rc->dev, nullptr, nullptr, gather_table_of(rc), rc->grid, rc->shape, rc->p.ng, rc->p.precision, 0, nullptr, 1,
                            s);
     };
     int64_t left = nsteps;
@@ -816,19 +823,20 @@ extern "C" pic_status pic_step_profiled(pic_run *r, int64_t nsteps, double *ms_p
     return st;
 }
 
-extern "C" pic_status pic_bandwidth_probe(void *a, void *b, int64_t n, int32_t reps, void *stream,
-                                          double *ms) {
+extern "C" pic_status pic_bandwidth_probe(void *a, void *b, int64_t n, int32_t reps, int32_t cached,
+                                          void *stream, double *ms) {
     if (!a || !b || !ms) return fail(PIC_EINVAL, "a, b and ms must not be NULL");
     if (n < 4 || n % 4 != 0 || reps < 1 || (uintptr_t)a % 16 || (uintptr_t)b % 16)
         return fail(PIC_EINVAL, "need n a positive multiple of 4, reps >= 1, 16-byte aligned arrays");
+    if (cached != 0 && cached != 1) return fail(PIC_EINVAL, "cached must be 0 or 1 (got %d)", cached);
     hipStream_t s = (hipStream_t)stream;
     const int cus = device_info().cus;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     hipError_t e = hipEventCreate(&e1);
-    if (e == hipSuccess) e = launch_swap(a, b, n / 4, cus, s);                    // warm-up
+    if (e == hipSuccess) e = launch_swap(a, b, n / 4, cus, cached != 0, s);       // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int k = 0; k < reps && e == hipSuccess; ++k) e = launch_swap(a, b, n / 4, cus, s);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) e = launch_swap(a, b, n / 4, cus, cached != 0, s);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float t = 0;
@@ -1181,6 +1189,7 @@ pic_status rebuild_schedule(pic_batch *b) {
     struct Chunk {
         int slot, tb, te, index, count;
         int64_t work;
+        const pic_run *run;
     };
     std::vector<Chunk> chunks;
     int64_t total = 0;
@@ -1202,7 +1211,7 @@ pic_status rebuild_schedule(pic_batch *b) {
             const int t1 = std::min(nt, t0 + per);
             // particles of tiles [t0, t1): whole tiles except the run's last
             const int64_t w = std::min<int64_t>((int64_t)t1 * tile, m.run->p.np) - (int64_t)t0 * tile;
-            chunks.push_back({m.slot, t0, t1, c, count, w + 4 * m.run->p.ng});
+            chunks.push_back({m.slot, t0, t1, c, count, w + 4 * m.run->p.ng, m.run});
         }
     }
     if ((int)chunks.size() > b->item_cap)
@@ -1227,7 +1236,7 @@ pic_status rebuild_schedule(pic_batch *b) {
     const int n = (int)chunks.size();
     for (int k = 0; k < n; ++k) {
         const Chunk &c = chunks[(size_t)k];
-        b->items_host[k] = {c.slot, c.tb, c.te, c.index, c.count, 0};
+        b->items_host[k] = {c.slot, c.tb, c.te, c.index, c.count, c.run->p.ng, gather_table_of(c.run)};
     }
     // The previous launch left next = 0; this copy is ordered after it.
     *b->queue_host = WorkQueue{0u, (uint32_t)n, {0u, 0u}};
@@ -1287,7 +1296,7 @@ pic_status enqueue_member_sorts(pic_batch *b) {
 // One batch step (particle pass, then the solve launch over the active
 // slots) on `stream`.
 hipError_t batch_launch(const pic_batch *b, hipStream_t stream, const StepEvents *ev = nullptr) {
-    return launch_step(b->table, b->items_dev, b->queue_dev, b->grid, b->shape, b->cfg.ng_max, PIC_FP32, 0,
+    return launch_step(b->table, b->items_dev, b->queue_dev, nullptr, b->grid, b->shape, b->cfg.ng_max, PIC_FP32, 0,
                        b->slots_dev, b->nsolve, stream, ev);
 }
 
@@ -1623,7 +1632,7 @@ pic_status batch_choose_shape(pic_batch *b) {
                     return rebuild_schedule(b) == PIC_OK ? hipSuccess : hipErrorInvalidValue;
                 },
                 [b](const LaunchShape &s) {
-                    return launch_particles(b->table, b->items_dev, b->queue_dev, b->grid, s, b->cfg.ng_max,
+                    return launch_particles(b->table, b->items_dev, b->queue_dev, nullptr, b->grid, s, b->cfg.ng_max,
                                             PIC_FP32, 0, b->stream);
                 },
                 &shape);

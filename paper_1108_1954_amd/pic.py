@@ -120,7 +120,7 @@ def load(path: str = LIB_PATH):
         "pic_phase_space": [vp, i32, i32, C.c_double, C.c_double, vp, C.POINTER(i64)],
         "pic_phase_space_noalloc": [vp, i32, i32, C.c_double, C.c_double, vp, C.POINTER(i64)],
         "pic_destroy": [vp],
-        "pic_bandwidth_probe": [vp, vp, i64, i32, vp, dptr],
+        "pic_bandwidth_probe": [vp, vp, i64, i32, i32, vp, dptr],
         "pic_batch_create": [C.POINTER(pic_batch_config), vp, C.POINTER(vp)],
         "pic_batch_admit": [vp, P, dptr, dptr, i64, C.POINTER(i64)],
         "pic_batch_step": [vp, i64],
@@ -329,11 +329,13 @@ def pic_batch_run(batch, run_id: int) -> C.c_void_p:
     return out
 
 
-def pic_bandwidth_probe(a: int, b: int, n: int, reps: int = 10, stream: Optional[int] = None) -> float:
+def pic_bandwidth_probe(a: int, b: int, n: int, reps: int = 10, stream: Optional[int] = None,
+                        cached: bool = False) -> float:
     """Mean ms of one swap of two device FP32 arrays of n values (device
-    pointers a, b): the particle pass's bytes without its work."""
+    pointers a, b): the particle pass's bytes without its work, with
+    non-temporal or (cached=True) ordinary cached accesses."""
     ms = C.c_double(0)
-    _check(load().pic_bandwidth_probe(a, b, int(n), int(reps), stream, C.byref(ms)))
+    _check(load().pic_bandwidth_probe(a, b, int(n), int(reps), int(bool(cached)), stream, C.byref(ms)))
     return ms.value
 
 

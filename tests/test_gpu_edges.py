@@ -1,6 +1,9 @@
 """Edge cases of the batch and the run API on the GPU: the largest grid in a
 batch, releasing an unfinished run and reusing its slot and memory,
-admission errors, and a history shorter than the run."""
+admission errors, a history shorter than the run, and the bandwidth probe's
+swap with both cache policies."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -116,6 +119,31 @@ def test_history_shorter_than_the_run():
         assert e.value.status == P.PIC_EINVAL
         for ra, rb in zip(a.raw(), b.raw()):
             np.testing.assert_array_equal(ra, rb)
+
+
+@pytest.mark.parametrize("cached", [False, True])
+def test_bandwidth_probe_swaps_the_arrays(cached):
+    """pic_bandwidth_probe launches the swap reps + 1 times (one warm-up):
+    the arrays end swapped for even reps and unchanged for odd reps, with
+    either cache policy, over a ragged vector count; bad arguments are
+    EINVAL."""
+    import torch
+    n = 4 * 300_001
+    a0 = torch.arange(n, dtype=torch.float32, device="cuda")
+    b0 = -a0 - 1.0
+    for reps, swapped in ((2, True), (1, False)):
+        a, b = a0.clone(), b0.clone()
+        torch.cuda.synchronize()
+        ms = P.pic_bandwidth_probe(a.data_ptr(), b.data_ptr(), n, reps=reps, stream=P.current_stream(),
+                                   cached=cached)
+        assert ms > 0
+        assert torch.equal(a, b0 if swapped else a0) and torch.equal(b, a0 if swapped else b0)
+    with pytest.raises(P.PicError) as e:
+        P.pic_bandwidth_probe(a0.data_ptr(), b0.data_ptr(), n - 2, reps=1, stream=P.current_stream())
+    assert e.value.status == P.PIC_EINVAL
+    out = ctypes.c_double(0)
+    st = P.load().pic_bandwidth_probe(a0.data_ptr(), b0.data_ptr(), n, 1, 2, P.current_stream(), ctypes.byref(out))
+    assert st == P.PIC_EINVAL                                  # cached must be 0 or 1
 
 
 @pytest.mark.slow
