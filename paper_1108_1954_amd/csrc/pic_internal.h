@@ -54,10 +54,11 @@ struct RunDev {
     int32_t cg_iters;            // CG iterations (solver 1)
 };
 
-// One unit of schedule: tiles [tile_begin, tile_end) of run `run`, which is
-// chunk `chunk` of the run's `nchunks` chunks in this launch; `ng` and
-// `table` repeat the run's grid size and gather-table address (fixed for the
-// run's life) so the pass can load the table without the run descriptor.
+// One unit of schedule: tiles tile_begin, tile_begin + tstride, ... below
+// tile_end of run `run`, which is chunk `chunk` of the run's `nchunks`
+// chunks in this launch; `ng` and `table` repeat the run's grid size and
+// gather-table address (fixed for the run's life) so the pass can load the
+// table without the run descriptor.
 struct WorkItem {
     int32_t run;
     int32_t tile_begin;
@@ -65,6 +66,8 @@ struct WorkItem {
     int32_t chunk;
     int32_t nchunks;
     int32_t ng;
+    int32_t tstride;
+    int32_t pad_;
     const void *table;
 };
 

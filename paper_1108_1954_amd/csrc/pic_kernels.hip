@@ -389,8 +389,9 @@ __device__ void merge_grid(unsigned long long *S, int ng, int rot_seed, unsigned
 }
 
 // Particle pass.  Single run (items == nullptr): workgroup b takes an
-// even share of the run's tiles.  Batch: workgroups take work items (chunks
-// of some run's tiles, largest first): workgroup b item b, then the next
+// even share of the run's tiles, or (order 1) every grid-th tile.  Batch:
+// workgroups take work items (chunks of some run's tiles, each chunk every
+// nchunks-th tile, largest first): workgroup b item b, then the next
 // ones from the shared queue until it is empty (see WorkQueue).  Any
 // workgroup may take any chunk: nothing a chunk computes depends on who
 // computes it (per-tile partials, integer grid sums).  A workgroup merges
@@ -442,6 +443,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
             chunk = wi.chunk;
             nchunks = wi.nchunks;
             ngt = wi.ng;
+            tstride = wi.tstride;
             tab = (const T *)wi.table;
         } else {
             ngt = ng_lds;

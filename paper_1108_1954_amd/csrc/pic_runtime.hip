@@ -1182,14 +1182,15 @@ pic_status batch_check(pic_batch *b) {
 }
 
 // Work list of the batched particle pass: each unfinished run is split into
-// chunks of about `target` particles (whole tiles), listed largest first;
-// the persistent workgroups take them in that order from the device queue,
+// chunks (whole tiles, dealt round robin), listed largest first; the
+// persistent workgroups take them in that order from the device queue,
 // which balances the load as it goes (longest-processing-time first).
 pic_status rebuild_schedule(pic_batch *b) {
     struct Chunk {
         int slot, tb, te, index, count;
         int64_t work;
         const pic_run *run;
+        int stride;
     };
     std::vector<Chunk> chunks;
     int64_t total = 0;
@@ -1201,17 +1202,35 @@ pic_status rebuild_schedule(pic_batch *b) {
     const int64_t target = std::max<int64_t>(1, total / std::max(1, 2 * b->grid));
     // at least a tile for every wavefront of the workgroup that takes a chunk
     const int min_tiles = std::max(1, b->shape.block / 64);
+    // A run's chunks: about `target` particles each (so that the queue
+    // balances the launch), never fewer tiles than wavefronts per workgroup
+    // (so that small batches keep every wavefront busy).  A run with tiles
+    // enough for max(kFrontChunks, its share by size) chunks of a tile per
+    // wavefront or more gets that many, and its tiles are dealt to its K chunks round
+    // robin (chunk c: tiles c, c + K, ...); the K chunks sit together in the
+    // list, so the K workgroups that take them sweep the run side by side:
+    // HBM serves such a front faster than workgroups that each stream a
+    // block of their own.  Other runs are cut into chunks of consecutive
+    // tiles.
+    constexpr int kFrontChunks = 8;
     for (auto &kv : b->members) {
         const Member &m = kv.second;
         if (m.launch_done <= b->launches) continue;
         const int tile = m.run->lay.tile, nt = m.run->lay.ntiles;
+        const int64_t by_size = (m.run->p.np + target - 1) / target;
+        const int64_t K = std::max<int64_t>(by_size, kFrontChunks);
+        if ((int64_t)nt >= K * min_tiles) {
+            for (int c = 0; c < (int)K; ++c)
+                chunks.push_back({m.slot, c, nt, c, (int)K, m.run->p.np / K + 4 * m.run->p.ng, m.run, (int)K});
+            continue;
+        }
         const int per = (int)std::max<int64_t>(min_tiles, (target + tile - 1) / tile);
         const int count = (nt + per - 1) / per;
         for (int c = 0, t0 = 0; t0 < nt; ++c, t0 += per) {
             const int t1 = std::min(nt, t0 + per);
             // particles of tiles [t0, t1): whole tiles except the run's last
             const int64_t w = std::min<int64_t>((int64_t)t1 * tile, m.run->p.np) - (int64_t)t0 * tile;
-            chunks.push_back({m.slot, t0, t1, c, count, w + 4 * m.run->p.ng, m.run});
+            chunks.push_back({m.slot, t0, t1, c, count, w + 4 * m.run->p.ng, m.run, 1});
         }
     }
     if ((int)chunks.size() > b->item_cap)
@@ -1236,7 +1255,7 @@ pic_status rebuild_schedule(pic_batch *b) {
     const int n = (int)chunks.size();
     for (int k = 0; k < n; ++k) {
         const Chunk &c = chunks[(size_t)k];
-        b->items_host[k] = {c.slot, c.tb, c.te, c.index, c.count, c.run->p.ng, gather_table_of(c.run)};
+        b->items_host[k] = {c.slot, c.tb, c.te, c.index, c.count, c.run->p.ng, c.stride, 0, gather_table_of(c.run)};
     }
     // The previous launch left next = 0; this copy is ordered after it.
     *b->queue_host = WorkQueue{0u, (uint32_t)n, {0u, 0u}};
@@ -1407,7 +1426,7 @@ extern "C" pic_status pic_batch_create(const pic_batch_config *cfg, void *stream
     const int occ = step_occupancy(b->shape, cfg->ng_max, PIC_FP32);
     b->grid = cfg->grid_blocks > 0 ? cfg->grid_blocks : d.cus * occ;
     b->grid_max = std::max(b->grid, d.cus * 16);      // room for any tuned shape
-    b->item_cap = 4 * b->grid_max + 4 * cfg->max_runs;
+    b->item_cap = 4 * b->grid_max + 16 * cfg->max_runs;
     bool ok = true;
     if (cfg->arena) {
         b->arena_base = (char *)cfg->arena;
