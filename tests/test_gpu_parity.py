@@ -322,6 +322,45 @@ def test_batched_runs_equal_the_same_runs_alone(monkeypatch, cached):
         P.pic_batch_destroy(b)
 
 
+def test_batch_with_runs_dealt_round_robin_equals_runs_alone(monkeypatch):
+    """A batch large enough for the work list to deal runs to chunks round
+    robin: 19.7M particles in seven runs (10M down to 100k, ng 64..2048) at
+    1024 threads (256 workgroups, 16 wavefronts each), so the chunk target
+    is about 38K particles and every run but the smallest gets K >= 8 chunks
+    of at least one tile per wavefront, taking tiles c, c + K, ... (the
+    100K-particle run keeps consecutive tiles).  State, grids and history
+    equal each run stepped alone, bit for bit."""
+    monkeypatch.setenv("PIC1D_BLOCK", "1024")
+    monkeypatch.setenv("PIC1D_UNROLL", "1")
+    sizes = [(10_000_000, 2048), (5_000_000, 1024), (2_500_000, 512), (1_200_000, 2048), (600_000, 256),
+             (300_000, 128), (100_000, 64)]
+    specs = [I.warm_two_stream_large(seed=40 + k, np_=n, ng=ng, nsteps=9, L=0.032 * ng)
+             for k, (n, ng) in enumerate(sizes)]
+    parts = [s.particles() for s in specs]
+    alone = []
+    for s, (x, v) in zip(specs, parts):
+        r, p = make_run(s, history=s.nsteps, x=x, v=v)
+        with r:
+            r.step(s.nsteps)
+            alone.append((r.raw(), r.grid(), r.history()))
+    b = P.pic_batch_create(2 << 30, 2048, max_runs=8, graph_steps=4, stream=P.current_stream())
+    try:
+        ids = [P.pic_batch_admit(b, P.make_params(s.L, s.ng, s.np_, s.dt, history_cap=s.nsteps), x, v, s.nsteps)
+               for s, (x, v) in zip(specs, parts)]
+        P.pic_batch_step(b, 20)
+        for rid, s, (raw, grid, hist) in zip(ids, specs, alone):
+            view = P.pic_batch_run(b, rid)
+            u, w = P.pic_read_raw(view, s.np_)
+            np.testing.assert_array_equal(u, raw[0])
+            np.testing.assert_array_equal(w, raw[1])
+            S, E, _ = P.pic_read_grid(view, s.ng)
+            np.testing.assert_array_equal(S, grid[0])
+            np.testing.assert_array_equal(E, grid[1])
+            np.testing.assert_array_equal(P.pic_read_history(view, 0, s.nsteps), hist)
+    finally:
+        P.pic_batch_destroy(b)
+
+
 def test_batch_mixing_solvers_and_step_counts_equals_runs_alone():
     """A batch of a run with the paper's CG solver (5 steps) and runs with the
     exact solver (14 to 20 steps): the solve launch shrinks as runs finish
