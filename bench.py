@@ -24,6 +24,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -68,10 +69,16 @@ def parse():
 
 
 def kernel_source_hash() -> str:
+    """Hash of the particle pass's code (its two source files without
+    comments and blank space), so that the counter figures in
+    profiles/traffic.json are used only for the code they were taken on."""
     h = hashlib.sha256()
     for f in ("pic_kernels.hip", "pic_internal.h"):
-        with open(os.path.join(ROOT, "paper_1108_1954_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1108_1954_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -266,7 +266,7 @@ __device__ void process_chunk(RunDev *R, int tb, int te, int tstride, unsigned l
     constexpr int SPB = kUnit / PER;                 // sub-blocks per block unit
     static_assert(kUnit % PER == 0, "a block unit holds whole sub-blocks");
     // Register sets in the load pipeline: three at one vector per lane
-    // (95 VGPRs, five waves per SIMD), two when the sub-blocks are wider
+    // (96 VGPRs, five waves per SIMD), two when the sub-blocks are wider
     // (a third measured no faster and spills at 1024 threads).  Four sets
     // at one vector cost a wave per SIMD and measured slower.
     constexpr int DEPTH = UNROLL == 1 ? 3 : 2;
