@@ -14,6 +14,7 @@ constexpr int kMaxNg = 8192;
 constexpr int kHistCols = 4;
 constexpr int kPartCols = 2;     // per tile: sum w_new^2, sum w_new
 constexpr int kWave = 64;
+constexpr int kFieldParts = 16;  // wavefronts of the largest field-solve workgroup (1024 threads)
 
 // Device-resident descriptor of one run.  Lives in device memory; the
 // kernels update step/counter/flags and the "now" diagnostics.
@@ -33,7 +34,8 @@ struct RunDev {
     void *sort_scratch;          // cell-sort count table and block sums, may be null
     int64_t np;
     int64_t hist_cap;
-    int64_t step;                // steps completed
+    int64_t step;                // steps completed (field solves; read by the particle pass)
+    int64_t diag_step;           // steps whose diagnostics are recorded (equals step between launches)
     int64_t step_target;         // no further steps once step == step_target
     int32_t ng;
     int32_t tile;                // particles per tile (multiple of kUnit)
@@ -46,7 +48,11 @@ struct RunDev {
     double ecoef;                // qm dt^2 / dx: E -> change of w per step
     double kcoef;                // (m/2) (dx/dt)^2: sum w^2 -> kinetic energy
     double pcoef;                // m dx/dt: sum w -> momentum
-    double field_now;            // W_E of the current field
+    // W_E of the field E^m is dx/2 times the sum, in index order, of
+    // field_part[m & 1][0 .. kFieldParts) (one entry per wavefront of the
+    // field solve, zero beyond its wavefronts), written by the solve that
+    // produces E^m
+    double field_part[2][kFieldParts];
     double kinetic_now;          // (m/2) sum v^2 of the current velocities
     double momentum_now;
     int64_t charge_now;          // sum_g S_g of the current positions

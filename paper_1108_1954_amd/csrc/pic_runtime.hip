@@ -282,6 +282,7 @@ void fill_constants(pic_run *r) {
     h.ng = p.ng;
     h.hist_cap = p.history_cap;
     h.step = 0;
+    h.diag_step = 0;
     h.step_target = INT64_MAX;
     h.tile = r->lay.tile;
     h.ntiles = r->lay.ntiles;
@@ -861,7 +862,13 @@ extern "C" pic_status pic_diagnostics(pic_run *r, pic_diag *diag, double *rho_ou
     diag->step = d.step;
     diag->time = (double)d.step * r->p.dt;
     diag->kinetic = d.kinetic_now;
-    diag->field = d.field_now;
+    {
+        // the field solve's per-wavefront sums of E^2, added in the same
+        // order as the device adds them for the history
+        double w = 0.0;
+        for (int k = 0; k < kFieldParts; ++k) w += d.field_part[d.step & 1][k];
+        diag->field = 0.5 * d.dx * w;
+    }
     diag->momentum = d.momentum_now;
     diag->charge_fixed_sum = d.charge_now;
     diag->net_charge = r->p.rho0 * r->p.L + r->Q * ((double)d.charge_now / 4294967296.0);

@@ -1,14 +1,16 @@
 // Field solve of the PIC step (gfx950): the second launch of every step.
 //
-// Workgroup b solves run runs[b] (idle and finished runs return at once):
-// it reads the fixed-point charge sums S the particle pass merged (the next
-// step's pass clears them), solves the periodic three-point Poisson problem
-// (Sec. 2.2) exactly, or with the paper's fixed-iteration CG when the run
-// asks for it, forms the central-difference node field, writes E^{n+1} in
-// FP64 and the gather table for the next particle pass, and records the
-// step's diagnostics from the per-tile partial sums.  Every reduction is a
-// fixed-order sum over the workgroup's threads, so the results depend only
-// on the run.
+// Two workgroups per run (idle and finished runs return at once).  The
+// field workgroup reads the fixed-point charge sums S the particle pass
+// merged (the next step's pass clears them), solves the periodic three-point
+// Poisson problem (Sec. 2.2) exactly, or with the paper's fixed-iteration CG
+// when the run asks for it, forms the central-difference node field, and
+// writes E^{n+1} in FP64, the gather table for the next particle pass and
+// the per-wavefront sums of E^2.  The diagnostics workgroup, beside it on
+// another CU, sums the per-tile partials of the particle pass and records
+// the step's diagnostics.  Neither reads what the other writes in the same
+// launch.  Every reduction is a fixed-order sum over the workgroup's
+// threads, so the results depend only on the run.
 #include "pic_internal.h"
 
 namespace pic1d {
@@ -141,11 +143,10 @@ __device__ double solve_exclusive_scan(double v, double *red2, int &par, int nth
 struct SolveView {
     const unsigned long long *S, *S_alt;   // the deposit to read (see solve_kernel), the other buffer
     float *Ehat;
-    double *Ehat64, *E64, *hist;
-    const double *tile_part;
-    int64_t step, step_target, hist_cap;
-    double dx, qfac, ecoef, kcoef, pcoef, kinetic_now, field_now;
-    int ng, ntiles, solver, cg_iters;
+    double *Ehat64, *E64;
+    int64_t step, step_target;
+    double dx, qfac, ecoef;
+    int ng, solver, cg_iters;
 };
 
 __device__ __forceinline__ SolveView solve_view(const RunDev *R) {
@@ -155,20 +156,12 @@ __device__ __forceinline__ SolveView solve_view(const RunDev *R) {
     v.Ehat = R->Ehat;
     v.Ehat64 = R->Ehat64;
     v.E64 = R->E64;
-    v.hist = R->hist;
-    v.tile_part = R->tile_part;
     v.step = R->step;
     v.step_target = R->step_target;
-    v.hist_cap = R->hist_cap;
     v.dx = R->dx;
     v.qfac = R->qfac;
     v.ecoef = R->ecoef;
-    v.kcoef = R->kcoef;
-    v.pcoef = R->pcoef;
-    v.kinetic_now = R->kinetic_now;
-    v.field_now = R->field_now;
     v.ng = R->ng;
-    v.ntiles = R->ntiles;
     v.solver = R->solver;
     v.cg_iters = R->cg_iters;
     return v;
@@ -395,8 +388,8 @@ __device__ __forceinline__ void cg_paper(const SolveView &V, double *D, double *
 constexpr int kSolveLds = kMaxNg + kMaxNg / 8;
 __device__ __forceinline__ int dpad(int g) { return g + (g >> 3); }
 
-__device__ __forceinline__ void solve_run(RunDev *R, const SolveView &V, double *D, double *red, long long *redi,
-                                          double *red3, bool prologue) {
+__device__ __forceinline__ void solve_field(RunDev *R, const SolveView &V, double *D, double *red, long long *redi,
+                                            double *red3, bool prologue) {
     const int ng = V.ng;
     const int tid = threadIdx.x;
     const int nthr = solve_threads(ng);
@@ -404,26 +397,17 @@ __device__ __forceinline__ void solve_run(RunDev *R, const SolveView &V, double 
     int par = 0;                                   // reduction buffers (see solve_sum)
     const unsigned long long *S = V.S;
     const bool cg = V.solver == 1;
-    const double *part = V.tile_part;
-    const int ntiles = V.ntiles;
     // Plain loads: this runs in the launch after the deposit, so the kernel
-    // boundary orders them after every workgroup's merge into S and its tile
-    // partials.  Every thread owns at most kSolvePer nodes (g = tid + k nthr,
-    // see solve_threads), and the loads of all of them and of the first
-    // kPartBatch tile partials (t = tid + k nthr) are issued before any is
-    // used: one memory round trip for the solve's inputs.  The sums keep the
-    // strided order g (t) = tid, tid + nthr, ...
+    // boundary orders them after every workgroup's merge into S.  Every
+    // thread owns at most kSolvePer nodes (g = tid + k nthr, see
+    // solve_threads), and the loads of all of them are issued before any is
+    // used: one memory round trip for the solve's input.  The sum keeps the
+    // strided order g = tid, tid + nthr, ...
     unsigned long long sv[kSolvePer];
-    f64x2 pv[kPartBatch];
 #pragma unroll
     for (int k = 0; k < kSolvePer; ++k) {
         const int g = tid + k * nthr;
         sv[k] = worker && g < ng ? S[g] : 0ull;
-    }
-#pragma unroll
-    for (int k = 0; k < kPartBatch; ++k) {
-        const int t = tid + k * nthr;
-        pv[k] = worker && t < ntiles ? *reinterpret_cast<const f64x2 *>(part + kPartCols * t) : f64x2{0.0, 0.0};
     }
     long long tot = 0;
 #pragma unroll
@@ -434,29 +418,8 @@ __device__ __forceinline__ void solve_run(RunDev *R, const SolveView &V, double 
             D[cg ? g : dpad(g)] = (double)sv[k];
         }
     }
-    // tile partials of the diagnostics, then any beyond the first batch
+    // exact sum_g S_g (and the barrier after which D holds every S_g)
     double a1 = 0.0, a2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < kPartBatch; ++k) {
-        a1 += pv[k].x;
-        a2 += pv[k].y;
-    }
-    if (worker) {
-        for (int t0 = tid + kPartBatch * nthr; t0 < ntiles; t0 += nthr * kPartBatch) {
-#pragma unroll
-            for (int k = 0; k < kPartBatch; ++k) {
-                const int t = t0 + k * nthr;
-                pv[k] = t < ntiles ? *reinterpret_cast<const f64x2 *>(part + kPartCols * t) : f64x2{0.0, 0.0};
-            }
-#pragma unroll
-            for (int k = 0; k < kPartBatch; ++k) {
-                a1 += pv[k].x;
-                a2 += pv[k].y;
-            }
-        }
-    }
-    // the three sums in one block reduction (and the barrier after which D
-    // holds every S_g): exact sum_g S_g and the two diagnostics sums
     solve_sum3(tot, a1, a2, redi, red3, nthr);
     const double meanS = (double)tot / (double)ng;
     const double ecoef = V.ecoef;
@@ -554,45 +517,95 @@ __device__ __forceinline__ void solve_run(RunDev *R, const SolveView &V, double 
                 if (j < n) we += e[j] * e[j];
         }
     }
-    we = 0.5 * V.dx * solve_sum(we, red, par, nthr);
+    // W_E of this field, E^m (m = 0 for the prologue, else step + 1), as one
+    // sum per wavefront: the reader (the next step's diagnostics workgroup,
+    // or the host) adds them in wavefront order, no barrier here
+    const double wsum = wave_sum(we);
+    const int m_par = prologue ? 0 : (int)((V.step + 1) & 1);
+    if ((tid & 63) == 0 && worker) R->field_part[m_par][tid >> 6] = wsum;
     if (tid == 0) {
-        const double kc = V.kcoef, pc = V.pcoef;
-        const double k_new = kc * a1;
-        if (!prologue) {
-            const int64_t n = V.step;
-            if (n < V.hist_cap) {
-                double *row = V.hist + (size_t)kHistCols * (size_t)n;
-                row[0] = 0.5 * (V.kinetic_now + k_new);    // KE^n, time-centred
-                row[1] = V.field_now;                      // W_E^n of the gathered field
-                row[2] = pc * a2;                          // P^{n+1/2}
-                row[3] = k_new;                            // K^{n+1/2}
-            }
-            R->step = n + 1;
-        }
-        R->kinetic_now = k_new;
-        R->momentum_now = pc * a2;
-        R->field_now = we;
+        if (!prologue) R->step = V.step + 1;
         R->charge_now = (int64_t)tot;
     }
 }
 
-// Second launch of a step: workgroup b solves run runs[slots[b]] (slots
-// null: runs[b]) for E^{n+1} and records the diagnostics; a slot of -1 and
-// runs that are idle or finished return at once.
+// The diagnostics of a step from the per-tile partial sums of the particle
+// pass (sum of w^2 and of w per tile, in tile order t = tid, tid + nthr, ...)
+// and the field energy the previous field solve left: the history row of
+// step n (KE^n time-centred, W_E^n of the gathered field, P^{n+1/2},
+// K^{n+1/2}) and the run's current kinetic energy and momentum.
+__device__ __forceinline__ void solve_diag(RunDev *R, long long *redi, double *red3, bool prologue) {
+    const int64_t n = R->diag_step;
+    if (!prologue && n >= R->step_target) return;
+    const int ng = R->ng;
+    const int tid = threadIdx.x;
+    const int nthr = solve_threads(ng);
+    const bool worker = tid < nthr;
+    const double *part = R->tile_part;
+    const int ntiles = R->ntiles;
+    double a1 = 0.0, a2 = 0.0;
+    if (worker) {
+        for (int t0 = tid; t0 < ntiles; t0 += nthr * kPartBatch) {
+            f64x2 pv[kPartBatch];
+#pragma unroll
+            for (int k = 0; k < kPartBatch; ++k) {
+                const int t = t0 + k * nthr;
+                pv[k] = t < ntiles ? *reinterpret_cast<const f64x2 *>(part + kPartCols * t) : f64x2{0.0, 0.0};
+            }
+#pragma unroll
+            for (int k = 0; k < kPartBatch; ++k) {
+                a1 += pv[k].x;
+                a2 += pv[k].y;
+            }
+        }
+    }
+    long long zero = 0;
+    solve_sum3(zero, a1, a2, redi, red3, nthr);
+    if (tid == 0) {
+        const double kc = R->kcoef, pc = R->pcoef;
+        const double k_new = kc * a1;
+        if (!prologue) {
+            if (n < R->hist_cap) {
+                // W_E^n: the sums of the solve that produced E^n, in order
+                const double *fp = R->field_part[n & 1];
+                double w = 0.0;
+                for (int k = 0; k < kFieldParts; ++k) w += fp[k];
+                double *row = R->hist + (size_t)kHistCols * (size_t)n;
+                row[0] = 0.5 * (R->kinetic_now + k_new);   // KE^n, time-centred
+                row[1] = 0.5 * R->dx * w;                  // W_E^n of the gathered field
+                row[2] = pc * a2;                          // P^{n+1/2}
+                row[3] = k_new;                            // K^{n+1/2}
+            }
+            R->diag_step = n + 1;
+        }
+        R->kinetic_now = k_new;
+        R->momentum_now = pc * a2;
+    }
+}
+
+// Second launch of a step: workgroups 2b and 2b + 1 handle run
+// runs[slots[b]] (slots null: runs[b]), the first solving for E^{n+1}, the
+// second recording the diagnostics; a slot of -1 and runs that are idle or
+// finished return at once.
 __global__ __launch_bounds__(kMaxSolveThreads) void solve_kernel(RunDev *runs, const int32_t *slots, int prologue) {
     __shared__ double D[kSolveLds];
     __shared__ double red[2 * kRedSlots];
     __shared__ long long redi[kRedSlots];
     __shared__ double red3[2 * kRedSlots];
-    const int slot = slots ? slots[blockIdx.x] : (int)blockIdx.x;
+    const int b = (int)(blockIdx.x >> 1);
+    const int slot = slots ? slots[b] : b;
     if (slot < 0) return;
     RunDev *R = runs + slot;
+    if (blockIdx.x & 1) {
+        solve_diag(R, redi, red3, prologue != 0);
+        return;
+    }
     SolveView V = solve_view(R);
     if (!prologue && V.step >= V.step_target) return;
     // this launch's deposit d (0 for the prologue, step + 1 otherwise) is in
     // S01[d & 1] (selected here: a select inside solve_run costs scratch)
     if (!prologue && ((V.step + 1) & 1)) V.S = V.S_alt;
-    solve_run(R, V, D, red, redi, red3, prologue != 0);
+    solve_field(R, V, D, red, redi, red3, prologue != 0);
 }
 
 }  // namespace
@@ -601,7 +614,8 @@ hipError_t launch_solve(RunDev *runs, const int32_t *slots, int nsolve, int prol
                         hipStream_t stream) {
     if (nsolve <= 0 || ng_max < 2 || ng_max > kMaxNg) return hipErrorInvalidValue;
     void *args[] = {(void *)&runs, (void *)&slots, (void *)&prologue};
-    return hipLaunchKernel((const void *)solve_kernel, dim3(nsolve), dim3(solve_threads(ng_max)), args, 0, stream);
+    return hipLaunchKernel((const void *)solve_kernel, dim3(2 * nsolve), dim3(solve_threads(ng_max)), args, 0,
+                           stream);
 }
 
 }  // namespace pic1d
