@@ -294,7 +294,8 @@ pic_status pic_destroy(pic_run *run);
  * A batch steps many independent runs of different (np, ng) with two
  * launches per step, replayed from a captured HIP graph: one persistent
  * particle pass over the chunks of every unfinished run, then one solve
- * launch with a workgroup per unfinished run.  Runs are admitted at any time against an HBM budget (bytes of the
+ * launch with two workgroups (field, diagnostics) per unfinished run.  Runs
+ * are admitted at any time against an HBM budget (bytes of the
  * batch's device arena), keep their state resident, stop at their own step
  * count and release their memory on pic_batch_release.  The result of a run
  * is the same alone and in any mix: its tiles, deposit and solve depend only
