@@ -87,22 +87,33 @@ __device__ V solve_sum(V v, V *red2, int &par, int nthr) {
     return sum_slots(red, nthr >> 6);
 }
 
-// The exact integer sum of `ti` and the sums of `a` and `b` over the first
-// nthr threads, each in the order of solve_sum, with a single barrier: the
-// wavefront totals go to slots of their own (ti_red, ab_red), which no other
-// reduction of the solve uses.  Every thread gets the three values.
-__device__ void solve_sum3(long long &ti, double &a, double &b, long long *ti_red, double *ab_red, int nthr) {
-    const long long wt = wave_sum(ti);
-    const double wa = wave_sum(a), wb = wave_sum(b);
+// The exact integer sum of `ti` (INT) and the sums of `a` and `b` (AB) over
+// the first nthr threads, each in the order of solve_sum, with a single
+// barrier: the wavefront totals go to slots of their own (ti_red, ab_red),
+// which no other reduction of the workgroup uses.  Every thread gets the
+// values.
+template <bool INT, bool AB>
+__device__ void solve_sums(long long &ti, double &a, double &b, long long *ti_red, double *ab_red, int nthr) {
+    long long wt = 0;
+    double wa = 0.0, wb = 0.0;
+    if constexpr (INT) wt = wave_sum(ti);
+    if constexpr (AB) {
+        wa = wave_sum(a);
+        wb = wave_sum(b);
+    }
     if ((threadIdx.x & 63) == 0 && (int)threadIdx.x < nthr) {
-        ti_red[threadIdx.x >> 6] = wt;
-        ab_red[threadIdx.x >> 6] = wa;
-        ab_red[kRedSlots + (threadIdx.x >> 6)] = wb;
+        if constexpr (INT) ti_red[threadIdx.x >> 6] = wt;
+        if constexpr (AB) {
+            ab_red[threadIdx.x >> 6] = wa;
+            ab_red[kRedSlots + (threadIdx.x >> 6)] = wb;
+        }
     }
     __syncthreads();
-    ti = sum_slots(ti_red, nthr >> 6);
-    a = sum_slots(ab_red, nthr >> 6);
-    b = sum_slots(ab_red + kRedSlots, nthr >> 6);
+    if constexpr (INT) ti = sum_slots(ti_red, nthr >> 6);
+    if constexpr (AB) {
+        a = sum_slots(ab_red, nthr >> 6);
+        b = sum_slots(ab_red + kRedSlots, nthr >> 6);
+    }
 }
 
 // Exclusive prefix sum over the first nthr threads in index order.  Inside a
@@ -419,8 +430,8 @@ __device__ __forceinline__ void solve_field(RunDev *R, const SolveView &V, doubl
         }
     }
     // exact sum_g S_g (and the barrier after which D holds every S_g)
-    double a1 = 0.0, a2 = 0.0;
-    solve_sum3(tot, a1, a2, redi, red3, nthr);
+    double unused_a = 0.0, unused_b = 0.0;
+    solve_sums<true, false>(tot, unused_a, unused_b, redi, red3, nthr);
     const double meanS = (double)tot / (double)ng;
     const double ecoef = V.ecoef;
     float *Ehat = V.Ehat;
@@ -559,8 +570,8 @@ __device__ __forceinline__ void solve_diag(RunDev *R, long long *redi, double *r
             }
         }
     }
-    long long zero = 0;
-    solve_sum3(zero, a1, a2, redi, red3, nthr);
+    long long unused = 0;
+    solve_sums<false, true>(unused, a1, a2, redi, red3, nthr);
     if (tid == 0) {
         const double kc = R->kcoef, pc = R->pcoef;
         const double k_new = kc * a1;
