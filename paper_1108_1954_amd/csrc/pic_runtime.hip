@@ -132,6 +132,9 @@ int default_tile(int64_t np) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Bytes after a single run's layout that hold its device descriptor.
+constexpr size_t kDescBytes = (sizeof(RunDev) + 255) / 256 * 256;
+
 struct Layout {
     size_t u, w, u_alt, w_alt, sort, S0, S1, Ehat, Ehat64, E64, part, hist, total;
     int tile, ntiles;
@@ -217,7 +220,7 @@ extern "C" pic_status pic_footprint(const pic_params *params, size_t *bytes) {
     pic_status st = validate(params);
     if (st != PIC_OK) return st;
     if (!bytes) return fail(PIC_EINVAL, "bytes is NULL");
-    *bytes = make_layout(params).total + 256;   // + room for the descriptor
+    *bytes = make_layout(params).total + kDescBytes;   // + the device descriptor
     return PIC_OK;
 }
 
@@ -582,7 +585,7 @@ pic_status create_run(const pic_params *params, void *dev_mem, size_t dev_bytes,
     r->p = *params;
     r->lay = make_layout(params);
     r->stream = (hipStream_t)stream;
-    const size_t need = r->lay.total + 256;
+    const size_t need = r->lay.total + kDescBytes;
     if (dev_mem) {
         if ((uintptr_t)dev_mem % 256 != 0) {
             delete r;
@@ -1534,7 +1537,7 @@ pic_status admit_run(pic_batch *b, const pic_params *params, const double *x0, c
     r->grid = single_run_grid(r, r->shape, b->cus);
     // Convert into pinned staging and queue upload, grid clearing,
     // descriptor and prologue on the batch stream; the host does not wait.
-    const size_t desc_bytes = (sizeof(RunDev) + 255) & ~(size_t)255;
+    const size_t desc_bytes = kDescBytes;
     const size_t part_bytes = ld ? 0 : (size_t)params->np * lay.esize;
     size_t gi = 0;
     st = get_staging(b, desc_bytes + 2 * part_bytes, &gi);

@@ -121,6 +121,33 @@ def test_history_shorter_than_the_run():
             np.testing.assert_array_equal(ra, rb)
 
 
+def test_run_stays_inside_its_footprint():
+    """A run created in caller memory of exactly pic_footprint() bytes (the
+    particle state, grids, history and the device descriptor) writes nothing
+    past it: a guard region after the span keeps its pattern through
+    creation, graph-replayed steps, a sort and the diagnostics."""
+    import torch
+    spec = I.warm_two_stream_large(seed=31, np_=50_001, ng=512, nsteps=12, L=0.032 * 512)
+    x, v = spec.particles()
+    p = P.make_params(spec.L, spec.ng, spec.np_, spec.dt, history_cap=spec.nsteps, sort_every=5)
+    need = P.pic_footprint(p)
+    guard = 64 << 10
+    buf = torch.empty(need + guard + 256, dtype=torch.uint8, device="cuda")
+    off = (-buf.data_ptr()) % 256
+    buf[off + need:off + need + guard].fill_(0xA5)
+    torch.cuda.synchronize()
+    h = P.pic_create(p, x, v, buf.data_ptr() + off, need, P.current_stream())
+    try:
+        P.pic_step_graph(h, spec.nsteps, 4)
+        d, _, _ = P.pic_diagnostics(h, 0)
+        assert d["step"] == spec.nsteps and d["flags"] == 0
+    finally:
+        P.pic_destroy(h)
+    torch.cuda.synchronize()
+    tail = buf[off + need:off + need + guard].cpu().numpy()
+    assert (tail == 0xA5).all(), f"{int((tail != 0xA5).sum())} guard bytes overwritten"
+
+
 @pytest.mark.parametrize("cached", [False, True])
 def test_bandwidth_probe_swaps_the_arrays(cached):
     """pic_bandwidth_probe launches the swap reps + 1 times (one warm-up):
