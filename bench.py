@@ -329,6 +329,20 @@ def main():
     P.pic_batch_destroy(b)
     log(f"batched: {ms_step:.3f} ms/step (events), {batched_rate:.4g} particle-steps/s (wall), "
         f"particle pass {ms_particle:.3f} ms, solve {ms_solve:.3f} ms")
+    # The measured bandwidth reference for these bytes: a plain swap of two
+    # FP32 arrays of total_np elements with the pass's byte pattern
+    # (non-temporal 16-byte loads and stores, one launch per swap).
+    nswap = total_np // 4 * 4
+    sa = torch.zeros(nswap, dtype=torch.float32, device="cuda")
+    sb = torch.ones(nswap, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    ms_swap = P.pic_bandwidth_probe(sa.data_ptr(), sb.data_ptr(), nswap, reps=20, stream=stream)
+    del sa, sb
+    swap = {"bytes": BYTES_PER_PSTEP * nswap, "ms": ms_swap, "GBps": BYTES_PER_PSTEP * nswap / (ms_swap * 1e6),
+            "pass_fraction_of_swap": ms_swap / ms_particle,
+            "note": "pic_bandwidth_probe: in-place swap of the same bytes, non-temporal 16-byte accesses, "
+                    "mean of 20 back-to-back launches; its rate depends on where the two arrays land in "
+                    "physical memory (398-479 us for these bytes across placements measured)"}
 
     # ---------------------------------------------------- plain per-run path
     plain = None
@@ -500,7 +514,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBPS, "traffic": measured_traffic("ensemble"),
                      "kernel": "step_kernel (particle pass)", "kernel_ms": ms_particle,
-                     "bytes_per_launch": BYTES_PER_PSTEP * total_np, "solve_ms": ms_solve},
+                     "bytes_per_launch": BYTES_PER_PSTEP * total_np, "solve_ms": ms_solve,
+                     "same_size_swap": swap},
         "plain": plain,
         "batched_vs_plain": (batched_rate / plain["value"]) if plain else None,
         "single_run": single,
