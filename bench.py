@@ -70,8 +70,10 @@ def parse():
 
 def kernel_source_hash() -> str:
     """Hash of the particle pass's code (its two source files without
-    comments and blank space), so that the counter figures in
-    profiles/traffic.json are used only for the code they were taken on."""
+    comments and blank space, and the compiler flags other than include
+    paths), so that the counter figures in profiles/traffic.json are used
+    only for the code they were taken on."""
+    from paper_1108_1954_amd import build as B
     h = hashlib.sha256()
     for f in ("pic_kernels.hip", "pic_internal.h"):
         with open(os.path.join(ROOT, "paper_1108_1954_amd", "csrc", f)) as fh:
@@ -79,6 +81,7 @@ def kernel_source_hash() -> str:
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
         h.update(" ".join(text.split()).encode())
+    h.update(" ".join(f for f in B.FLAGS if not f.startswith("-I")).encode())
     return h.hexdigest()[:16]
 
 

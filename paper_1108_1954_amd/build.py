@@ -24,6 +24,10 @@ FLAGS = [
     "-shared",
     "-ffp-contract=off",                 # every FMA in the kernels is explicit
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # kernel arguments preloaded into SGPRs at wave launch, so a launch's first
+    # dependent load (work item, run descriptor, gather table) goes out without
+    # waiting for a scalar load of its arguments (1-2% on launches of 10-30 us)
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Wall",
     f"-I{os.path.join(ROOT, 'include')}",
 ]
