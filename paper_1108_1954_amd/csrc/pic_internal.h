@@ -80,7 +80,8 @@ struct WorkItem {
 // Work queue of a batched particle pass (device memory): workgroup b takes
 // item b first, then items grid, grid + 1, ... in list order through the
 // ticket counter `next`; the workgroup that draws the launch's last ticket
-// resets it to 0 for the next launch.
+// resets it to 0 for the next launch.  With nitems <= grid nothing is queued
+// and no workgroup draws (`next` stays 0).
 struct WorkQueue {
     uint32_t next;
     uint32_t nitems;

@@ -417,15 +417,18 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(RunDev *runs, const WorkIte
         if (items && round == 0) {
             it = blockIdx.x;                          // first item: no queue traffic
         } else if (items) {
+            // No more items than workgroups: every item was a first item and
+            // nothing is queued, so no workgroup draws a ticket (a returning
+            // atomic on one address at every workgroup's end) and `next`
+            // stays 0 for the next launch.
+            if (nitems <= grid) break;
             if (threadIdx.x == 0) {
                 // Tickets 0, 1, ... map to items grid, grid + 1, ...; every
-                // workgroup that had a first item draws exactly one ticket
-                // past the list and stops, so the holder of the last ticket
-                // knows that no other workgroup touches `next` again.
+                // workgroup draws exactly one ticket past the list and
+                // stops, so the holder of the last ticket, nitems - 1, knows
+                // that no other workgroup touches `next` again.
                 const uint32_t t = atomicAdd(&queue->next, 1u);
-                const uint32_t fetching = nitems < grid ? nitems : grid;
-                const uint32_t more = nitems > grid ? nitems - grid : 0u;
-                if (t == more + fetching - 1u) atomicExch(&queue->next, 0u);
+                if (t == nitems - 1u) atomicExch(&queue->next, 0u);
                 s_item = grid + t;
             }
             __syncthreads();
