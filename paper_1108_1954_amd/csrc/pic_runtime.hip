@@ -1185,6 +1185,12 @@ struct pic_batch {
 
 namespace {
 
+// Persistent workgroups of the batch's particle pass for a launch shape: the
+// configured count, else every CU at the shape's occupancy.
+int batch_grid(const pic_batch *b, const LaunchShape &s) {
+    return b->cfg.grid_blocks > 0 ? b->cfg.grid_blocks : b->cus * step_occupancy(s, b->cfg.ng_max, PIC_FP32);
+}
+
 pic_status batch_check(pic_batch *b) {
     if (!b) return fail(PIC_EINVAL, "batch is NULL");
     if (b->error) return fail(PIC_ESTATE, "batch is in an error state after a device error");
@@ -1657,7 +1663,7 @@ pic_status batch_choose_shape(pic_batch *b) {
                 key, PIC_FP32, false, b->stream,
                 [b](const LaunchShape &s) {
                     b->shape = s;
-                    b->grid = b->cus * step_occupancy(s, b->cfg.ng_max, PIC_FP32);
+                    b->grid = batch_grid(b, s);
                     return rebuild_schedule(b) == PIC_OK ? hipSuccess : hipErrorInvalidValue;
                 },
                 [b](const LaunchShape &s) {
@@ -1680,7 +1686,7 @@ pic_status batch_choose_shape(pic_batch *b) {
     }
     b->shape = shape;
     HIP_TRY(step_prepare(b->shape, PIC_FP32));
-    b->grid = b->cus * step_occupancy(b->shape, b->cfg.ng_max, PIC_FP32);
+    b->grid = batch_grid(b, b->shape);
     b->tuned_key = key;
     // Tuning launches change the work list; the graph only has to go when
     // the launch itself (shape or grid) changed.

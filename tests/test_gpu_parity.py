@@ -361,6 +361,53 @@ def test_batch_with_runs_dealt_round_robin_equals_runs_alone(monkeypatch):
         P.pic_batch_destroy(b)
 
 
+@pytest.mark.parametrize("forced", [True, False])
+def test_batch_switching_between_queued_and_unqueued_launches(monkeypatch, forced):
+    """Three persistent workgroups (the configured grid, also when the batch
+    tunes its shape) and runs of 8K-15K particles, about one work item each:
+    six runs make a work list longer than the grid (items 3.. come through
+    the queue's tickets); when three of them have finished the list fits the
+    grid (nothing is queued, no ticket is drawn); two admissions lengthen it
+    again.  Both kinds of launch must leave the queue's counter at 0 for the
+    next, and every run equals the same run alone, bit for bit."""
+    import torch
+    if forced:
+        monkeypatch.setenv("PIC1D_BLOCK", "512")
+        monkeypatch.setenv("PIC1D_UNROLL", "1")
+    sizes = [(15_000, 1024), (9_000, 64), (12_000, 256), (8_000, 512), (14_000, 128), (10_000, 1024),
+             (13_000, 64), (11_000, 512)]
+    steps = [4, 6, 8, 14, 16, 18, 9, 11]
+    specs = [I.warm_two_stream_large(seed=60 + k, np_=n, ng=ng, nsteps=st, L=0.032 * ng)
+             for k, ((n, ng), st) in enumerate(zip(sizes, steps))]
+    parts = [s.particles() for s in specs]
+    alone = []
+    for s, (x, v) in zip(specs, parts):
+        r, p = make_run(s, history=s.nsteps, x=x, v=v)
+        with r:
+            r.step(s.nsteps)
+            alone.append((r.raw(), r.grid(), r.history()))
+    b = P.pic_batch_create(1 << 30, 2048, max_runs=16, graph_steps=2, grid_blocks=3, stream=P.current_stream())
+    try:
+        params = [P.make_params(s.L, s.ng, s.np_, s.dt, history_cap=s.nsteps) for s in specs]
+        ids = [P.pic_batch_admit(b, params[k], *parts[k], specs[k].nsteps) for k in range(6)]
+        P.pic_batch_step(b, 10)                        # runs of 4, 6 and 8 steps finish
+        torch.cuda.synchronize()                       # the poll reports completed device work only
+        assert sorted(P.pic_batch_poll(b)) == sorted(ids[:3])
+        ids += [P.pic_batch_admit(b, params[k], *parts[k], specs[k].nsteps) for k in (6, 7)]
+        P.pic_batch_step(b, 30)
+        for rid, s, (raw, grid, hist) in zip(ids, specs, alone):
+            view = P.pic_batch_run(b, rid)
+            u, w = P.pic_read_raw(view, s.np_)
+            np.testing.assert_array_equal(u, raw[0])
+            np.testing.assert_array_equal(w, raw[1])
+            S, E, _ = P.pic_read_grid(view, s.ng)
+            np.testing.assert_array_equal(S, grid[0])
+            np.testing.assert_array_equal(E, grid[1])
+            np.testing.assert_array_equal(P.pic_read_history(view, 0, s.nsteps), hist)
+    finally:
+        P.pic_batch_destroy(b)
+
+
 def test_batch_mixing_solvers_and_step_counts_equals_runs_alone():
     """A batch of a run with the paper's CG solver (5 steps) and runs with the
     exact solver (14 to 20 steps): the solve launch shrinks as runs finish
