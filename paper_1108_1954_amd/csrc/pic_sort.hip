@@ -70,6 +70,51 @@ __device__ __forceinline__ void count_key(uint32_t *h, int key) {
     }
 }
 
+// 16-byte vectors of the particle state (4 FP32 or 2 FP64 values).
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    typedef float __attribute__((ext_vector_type(4))) type;
+    static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+    typedef double __attribute__((ext_vector_type(2))) type;
+    static constexpr int n = 2;
+};
+
+// h[key] += 1 for the keys of u[i0, i1), counted by `nthr` threads (thread
+// `tid` of them) in 16-byte vectors, kCountVecs per thread in flight, then
+// the last partial vector one value per thread.  Counting does not depend on
+// order, so a thread may take any values.  i0 must be a multiple of the
+// vector width.
+constexpr int kCountVecs = 4;
+template <typename T>
+__device__ __forceinline__ void count_range(uint32_t *h, const T *u, int64_t i0, int64_t i1, int tid, int nthr,
+                                            int ng) {
+    using V = typename Vec16<T>::type;
+    constexpr int VEC = Vec16<T>::n;
+    const int64_t nv = (i1 - i0) / VEC;               // whole vectors
+    const V *uv = reinterpret_cast<const V *>(u + i0);
+    for (int64_t v0 = tid; v0 < nv; v0 += (int64_t)nthr * kCountVecs) {
+        V buf[kCountVecs];
+#pragma unroll
+        for (int q = 0; q < kCountVecs; ++q) {
+            const int64_t v = v0 + (int64_t)q * nthr;
+            if (v < nv) buf[q] = uv[v];
+        }
+#pragma unroll
+        for (int q = 0; q < kCountVecs; ++q) {
+            if (v0 + (int64_t)q * nthr < nv) {
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) count_key(h, cell_key(buf[q][j], ng));
+            }
+        }
+    }
+    for (int64_t i = i0 + nv * VEC + tid; i < i1; i += nthr) count_key(h, cell_key(u[i], ng));
+}
+
 template <typename T>
 __global__ __launch_bounds__(kSortBlock) void sort_count_kernel(const RunDev *R, int seg, int nseg,
                                                                 uint32_t *table) {
@@ -80,8 +125,8 @@ __global__ __launch_bounds__(kSortBlock) void sort_count_kernel(const RunDev *R,
     for (int k = threadIdx.x; k <= ng; k += kSortBlock) h[k] = 0;
     __syncthreads();
     const int s = blockIdx.x;
-    const int64_t b0 = (int64_t)s * seg, b1 = min(np, b0 + seg);
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += kSortBlock) count_key(h, cell_key(u[i], ng));
+    const int64_t b0 = (int64_t)s * seg, b1 = min(np, b0 + seg);   // seg: a multiple of 1024
+    count_range<T>(h, u, b0, b1, (int)threadIdx.x, kSortBlock, ng);
     __syncthreads();
     for (int k = threadIdx.x; k <= ng; k += kSortBlock) table[(size_t)k * nseg + s] = h[k];
 }
@@ -184,7 +229,7 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(RunDev *R, int
     uint32_t *mine = cw + wave * nk;
     for (int k = threadIdx.x; k < kSortWaves * nk; k += kSortBlock) cw[k] = 0;
     __syncthreads();
-    for (int64_t i = w0 + lane; i < w1; i += 64) count_key(mine, cell_key(u[i], ng));
+    count_range<T>(mine, u, w0, w1, lane, 64, ng);   // w0 - b0: a multiple of 64
     __syncthreads();
     // first destination of (key, wavefront): the segment's offset plus the
     // counts of the earlier wavefronts
@@ -197,11 +242,23 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(RunDev *R, int
         }
     }
     __syncthreads();
+    // Groups of 64 consecutive particles in input order (the ranks below make
+    // the sort stable); the next group's values are loaded while this one is
+    // placed (loading more groups ahead measured slower).
     uint32_t bad = 0;
+    T nu = T(0), nw = T(0);
+    if (w0 + lane < w1) {
+        nu = u[w0 + lane];
+        nw = w[w0 + lane];
+    }
     for (int64_t g = w0; g < w1; g += 64) {
         const int64_t i = g + lane;
+        const T su = nu, sw = nw;
+        if (i + 64 < w1) {
+            nu = u[i + 64];
+            nw = w[i + 64];
+        }
         if (i < w1) {
-            const T su = u[i], sw = w[i];
             const int key = cell_key(su, ng);
             const unsigned long long peers = match_key(key);
             const int leader = __builtin_ctzll(peers);
