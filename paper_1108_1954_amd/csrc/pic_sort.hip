@@ -88,7 +88,7 @@ struct Vec16<double> {
 // `tid` of them) in 16-byte vectors, kCountVecs per thread in flight, then
 // the last partial vector one value per thread.  Counting does not depend on
 // order, so a thread may take any values.  i0 must be a multiple of the
-// vector width.
+// vector width (the particle arrays start 256-byte aligned).
 constexpr int kCountVecs = 4;
 template <typename T>
 __device__ __forceinline__ void count_range(uint32_t *h, const T *u, int64_t i0, int64_t i1, int tid, int nthr,
