@@ -70,6 +70,18 @@ __device__ __forceinline__ void count_key(uint32_t *h, int key) {
     }
 }
 
+// Segment of workgroup b: workgroups are dispatched to the device's 8 XCDs
+// in turn (b mod 8), so consecutive segments, which share the lines of the
+// key-major count table, go to workgroups of one XCD, whose L2 then holds
+// whole lines.  A bijection of [0, nseg) for any nseg: XCD x takes a
+// contiguous range of nseg / 8 segments (one more for the first nseg mod 8).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int segment_of(int b, int nseg) {
+    const int x = b % kXcds, local = b / kXcds;
+    const int full = nseg / kXcds, rem = nseg % kXcds;
+    return x < rem ? x * (full + 1) + local : rem * (full + 1) + (x - rem) * full + local;
+}
+
 // 16-byte vectors of the particle state (4 FP32 or 2 FP64 values).
 template <typename T>
 struct Vec16;
@@ -124,7 +136,7 @@ __global__ __launch_bounds__(kSortBlock) void sort_count_kernel(const RunDev *R,
     const T *u = (const T *)R->u;
     for (int k = threadIdx.x; k <= ng; k += kSortBlock) h[k] = 0;
     __syncthreads();
-    const int s = blockIdx.x;
+    const int s = segment_of((int)blockIdx.x, nseg);
     const int64_t b0 = (int64_t)s * seg, b1 = min(np, b0 + seg);   // seg: a multiple of 1024
     count_range<T>(h, u, b0, b1, (int)threadIdx.x, kSortBlock, ng);
     __syncthreads();
@@ -222,7 +234,7 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(RunDev *R, int
     const T *w = (const T *)R->w;
     T *uo = (T *)R->u_alt;
     T *wo = (T *)R->w_alt;
-    const int s = blockIdx.x, wave = threadIdx.x >> 6, lane = lane_id();
+    const int s = segment_of((int)blockIdx.x, nseg), wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t b0 = (int64_t)s * seg, b1 = min(np, b0 + seg);
     const int64_t sub = (b1 - b0 + kSortBlock - 1) / kSortBlock * 64;    // per wavefront, multiple of 64
     const int64_t w0 = min(b1, b0 + wave * sub), w1 = min(b1, w0 + sub);
