@@ -205,22 +205,46 @@ __global__ __launch_bounds__(kTopBlock) void scan_top_kernel(uint32_t *bsum, int
     }
 }
 
+// Each thread's kScanItems consecutive entries move as 16-byte vectors when
+// they are all inside the table (the table starts 256-byte aligned and b0 is
+// a multiple of kScanItems), one by one at its end.
 __global__ __launch_bounds__(kScanBlock) void scan_down_kernel(uint32_t *a, int64_t n, const uint32_t *bsum) {
+    typedef uint32_t __attribute__((ext_vector_type(4))) u32x4;
+    static_assert(kScanItems % 4 == 0, "whole vectors per thread");
     __shared__ uint32_t red[kScanBlock / 64];
     const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const bool whole = b0 + kScanItems <= n;
     uint32_t v[kScanItems];
+    if (whole) {
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q) {
+            const u32x4 t = *(const u32x4 *)(a + b0 + 4 * q);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[4 * q + j] = t[j];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) v[i] = b0 + i < n ? a[b0 + i] : 0u;
+    }
     uint32_t sum = 0;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        v[i] = b0 + i < n ? a[b0 + i] : 0u;
-        sum += v[i];
-    }
+    for (int i = 0; i < kScanItems; ++i) sum += v[i];
     uint32_t tot;
     uint32_t run = bsum[blockIdx.x] + block_exclusive_scan(sum, red, &tot);
+    uint32_t out[kScanItems];
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        if (b0 + i < n) a[b0 + i] = run;
+        out[i] = run;
         run += v[i];
+    }
+    if (whole) {
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q)
+            *(u32x4 *)(a + b0 + 4 * q) = u32x4{out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]};
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i)
+            if (b0 + i < n) a[b0 + i] = out[i];
     }
 }
 
