@@ -33,6 +33,7 @@ constexpr int kScanItems = 16;                  // consecutive elements per thre
 constexpr int kScanTile = kScanBlock * kScanItems;
 constexpr int kTopBlock = 1024;
 constexpr int kKeyBits = 14;                    // keys <= kMaxNg = 2^13
+constexpr int kScatterRing = 4;                 // 64-particle groups in flight per wavefront in the scatter
 
 template <typename T>
 __device__ __forceinline__ int cell_key(T s, int ng) {
@@ -82,6 +83,11 @@ __device__ __forceinline__ int segment_of(int b, int nseg) {
     return x < rem ? x * (full + 1) + local : rem * (full + 1) + (x - rem) * full + local;
 }
 
+// Particle arrays as global-memory pointers: the descriptor holds generic
+// ones, whose accesses the compiler would issue as flat operations, which
+// every LDS wait in the scatter loop would also wait for.
+#define GLOBAL_AS __attribute__((address_space(1)))
+
 // 16-byte vectors of the particle state (4 FP32 or 2 FP64 values).
 template <typename T>
 struct Vec16;
@@ -103,12 +109,12 @@ struct Vec16<double> {
 // vector width (the particle arrays start 256-byte aligned).
 constexpr int kCountVecs = 4;
 template <typename T>
-__device__ __forceinline__ void count_range(uint32_t *h, const T *u, int64_t i0, int64_t i1, int tid, int nthr,
-                                            int ng) {
+__device__ __forceinline__ void count_range(uint32_t *h, const GLOBAL_AS T *u, int64_t i0, int64_t i1, int tid,
+                                            int nthr, int ng) {
     using V = typename Vec16<T>::type;
     constexpr int VEC = Vec16<T>::n;
     const int64_t nv = (i1 - i0) / VEC;               // whole vectors
-    const V *uv = reinterpret_cast<const V *>(u + i0);
+    const GLOBAL_AS V *uv = (const GLOBAL_AS V *)(u + i0);
     for (int64_t v0 = tid; v0 < nv; v0 += (int64_t)nthr * kCountVecs) {
         V buf[kCountVecs];
 #pragma unroll
@@ -133,7 +139,7 @@ __global__ __launch_bounds__(kSortBlock) void sort_count_kernel(const RunDev *R,
     extern __shared__ uint32_t h[];             // [ng + 1]
     const int ng = R->ng;
     const int64_t np = R->np;
-    const T *u = (const T *)R->u;
+    const GLOBAL_AS T *u = (const GLOBAL_AS T *)R->u;
     for (int k = threadIdx.x; k <= ng; k += kSortBlock) h[k] = 0;
     __syncthreads();
     const int s = segment_of((int)blockIdx.x, nseg);
@@ -248,16 +254,43 @@ __global__ __launch_bounds__(kScanBlock) void scan_down_kernel(uint32_t *a, int6
     }
 }
 
+// Place one 64-particle group (lanes with `valid` set) in input order: lanes
+// with equal keys are ranked by lane, after the wavefront's earlier
+// particles of that key (`mine`).  A destination outside [0, np), which the
+// count and the scan make impossible, goes to the last slot instead (memory
+// stays in bounds) and sets `bad`; the store is issued for every valid lane,
+// so the loop's memory operations do not depend on the data.
+template <typename T>
+__device__ __forceinline__ void place_group(T su, T sw, uint32_t *mine, GLOBAL_AS T *uo, GLOBAL_AS T *wo,
+                                            int64_t np, int ng, int lane, uint32_t &bad) {
+    const int key = cell_key(su, ng);
+    const unsigned long long peers = match_key(key);
+    const int leader = __builtin_ctzll(peers);
+    const uint32_t rank = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+    uint32_t base = 0;
+    if (lane == leader) {
+        base = mine[key];
+        mine[key] = base + (uint32_t)__popcll(peers);
+    }
+    base = (uint32_t)__shfl((int)base, leader);
+    const uint32_t dst = base + rank;
+    const bool ok = dst < (uint64_t)np;
+    bad |= ok ? 0u : 1u;
+    const int64_t d = ok ? (int64_t)dst : np - 1;
+    uo[d] = su;
+    wo[d] = sw;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(RunDev *R, int seg, int nseg,
                                                                   const uint32_t *offs) {
     extern __shared__ uint32_t cw[];            // [kSortWaves][ng + 1]
     const int ng = R->ng, nk = ng + 1;
     const int64_t np = R->np;
-    const T *u = (const T *)R->u;
-    const T *w = (const T *)R->w;
-    T *uo = (T *)R->u_alt;
-    T *wo = (T *)R->w_alt;
+    const GLOBAL_AS T *u = (const GLOBAL_AS T *)R->u;
+    const GLOBAL_AS T *w = (const GLOBAL_AS T *)R->w;
+    GLOBAL_AS T *uo = (GLOBAL_AS T *)R->u_alt;
+    GLOBAL_AS T *wo = (GLOBAL_AS T *)R->w_alt;
     const int s = segment_of((int)blockIdx.x, nseg), wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t b0 = (int64_t)s * seg, b1 = min(np, b0 + seg);
     const int64_t sub = (b1 - b0 + kSortBlock - 1) / kSortBlock * 64;    // per wavefront, multiple of 64
@@ -278,39 +311,42 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(RunDev *R, int
         }
     }
     __syncthreads();
-    // Groups of 64 consecutive particles in input order (the ranks below make
-    // the sort stable); the next group's values are loaded while this one is
-    // placed (loading more groups ahead measured slower).
+    // Groups of 64 consecutive particles in input order, kScatterRing of
+    // them in registers: group g is placed from set g mod kScatterRing, which
+    // is refilled with group g + kScatterRing at once (addresses past the
+    // wavefront's range are clamped into it, so every load is issued), so
+    // the loads of the next groups are in flight while one is placed.  Whole
+    // rounds of whole groups run without data-dependent branches around
+    // memory operations; the rest, from the same registers, lane by lane.
     uint32_t bad = 0;
-    T nu = T(0), nw = T(0);
-    if (w0 + lane < w1) {
-        nu = u[w0 + lane];
-        nw = w[w0 + lane];
-    }
-    for (int64_t g = w0; g < w1; g += 64) {
-        const int64_t i = g + lane;
-        const T su = nu, sw = nw;
-        if (i + 64 < w1) {
-            nu = u[i + 64];
-            nw = w[i + 64];
+    if (w1 > w0) {
+        const int64_t ngroups = (w1 - w0 + 63) / 64, nfull = (w1 - w0) / 64;
+        const int64_t last = w1 - 1;
+        T bu[kScatterRing], bw[kScatterRing];
+#pragma unroll
+        for (int d = 0; d < kScatterRing; ++d) {
+            const int64_t i = min(w0 + d * 64 + lane, last);
+            bu[d] = u[i];
+            bw[d] = w[i];
         }
-        if (i < w1) {
-            const int key = cell_key(su, ng);
-            const unsigned long long peers = match_key(key);
-            const int leader = __builtin_ctzll(peers);
-            const uint32_t rank = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
-            uint32_t base = 0;
-            if (lane == leader) {
-                base = mine[key];
-                mine[key] = base + (uint32_t)__popcll(peers);
+        const int64_t rounds = nfull / kScatterRing;
+        for (int64_t r = 0; r < rounds; ++r) {
+#pragma unroll
+            for (int d = 0; d < kScatterRing; ++d) {
+                const int64_t i = w0 + (r * kScatterRing + d) * 64 + lane;
+                const T su = bu[d], sw = bw[d];
+                const int64_t ahead = min(i + 64 * kScatterRing, last);
+                bu[d] = u[ahead];
+                bw[d] = w[ahead];
+                place_group<T>(su, sw, mine, uo, wo, np, ng, lane, bad);
             }
-            base = (uint32_t)__shfl((int)base, leader);
-            const uint32_t dst = base + rank;
-            if (dst < (uint64_t)np) {
-                uo[dst] = su;
-                wo[dst] = sw;
-            } else {
-                bad = 1;
+        }
+#pragma unroll
+        for (int d = 0; d < kScatterRing; ++d) {
+            const int64_t g = rounds * kScatterRing + d;
+            if (g < ngroups) {
+                const int64_t i = w0 + g * 64 + lane;
+                if (i < w1) place_group<T>(bu[d], bw[d], mine, uo, wo, np, ng, lane, bad);
             }
         }
     }
